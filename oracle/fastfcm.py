@@ -1,0 +1,299 @@
+"""Fast FCM, plain FP64 on the CPU: the algorithm of Sec. 4, step by step.
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+The steps are those of Sec. 4 in the paper's order: spatial hashing, sorting
+into cell lists, applying the modified spreading operator J~^dagger (with the
+torque spreading N~^dagger of Sec. 3.4), the inverse Stokes operator in
+Fourier space (Sec. 2.1, App. A), the interpolation operators J~ and N~, and
+the pairwise correction for pairs closer than R_c, plus the self corrections
+of App. B.  numpy's FFT serves as the Fourier transform; nothing is blocked,
+fused or reordered.
+
+Grid conventions (the paper leaves them open; these readings are part of the
+library's contract and are checked only GPU-against-oracle):
+
+* grid points sit at x_g = (i, j, k) * dx, i, j, k = 0..M-1, dx = L / M, on the
+  periodic box [0, L)^3 (Sec. 2.1);
+* the M_G support points of a particle at coordinate Y along one axis are
+  start, ..., start + M_G - 1 (indices mod M) with
+  start = floor(Y/dx - M_G/2) + 1, and the displacement used in the kernel is
+  d = (start + j) dx - Y, not a minimum image;
+* for even M every Fourier mode whose index equals M/2 along any axis is set
+  to zero in the Stokes solve (the projection is odd in that component, so a
+  real field cannot represent it), and the k = 0 mode is zero;
+* Omega is formed from the real-space gradient of the torque Gaussian
+  (integration by parts of (1/2) curl u), which makes N~ the exact transpose of
+  N~^dagger on the grid.
+"""
+
+from dataclasses import dataclass
+import math
+
+import numpy as np
+
+from . import closed_forms as cf
+
+
+@dataclass
+class Params:
+    """Fast-FCM parameters (Sec. 5): box L, grid M per axis, support M_G,
+    particle radius a, modified widths Sigma (force) and Sigma_D (torque,
+    Sec. 3.4; the paper takes Sigma_D = Sigma), cut-off R_c, viscosity eta."""
+    L: float
+    M: int
+    a: float
+    Sigma: float
+    M_G: int
+    R_c: float
+    eta: float = 1.0
+    Sigma_D: float = None
+
+    def __post_init__(self):
+        if self.Sigma_D is None:
+            self.Sigma_D = self.Sigma
+
+    @property
+    def sigma(self):
+        """FCM force width, a = sigma sqrt(pi) (Sec. 2)."""
+        return self.a / math.sqrt(math.pi)
+
+    @property
+    def sigma_D(self):
+        """FCM torque width sigma_D = a / (6 sqrt pi)^(1/3) (Sec. 3.4)."""
+        return self.a / (6.0 * math.sqrt(math.pi)) ** (1.0 / 3.0)
+
+    @property
+    def dx(self):
+        return self.L / self.M
+
+
+# --- Sec. 4, steps 1-2: spatial hashing and cell lists ---------------------
+
+def wrap(Y, L):
+    """Map positions into the periodic box [0, L)."""
+    Yw = np.mod(np.asarray(Y, dtype=np.float64), L)
+    Yw[Yw >= L] = 0.0
+    return Yw
+
+
+def cell_counts(L, R_c):
+    """Cells per direction m = max(int(L / R_c), 3) (Sec. 4, spatial hashing)."""
+    return max(int(L / R_c), 3)
+
+
+def hash_particles(Y, L, m):
+    """Cell index x_c + (y_c + z_c m_y) m_x of every particle (Sec. 4)."""
+    c = np.floor(wrap(Y, L) / (L / m)).astype(np.int64)
+    c = np.minimum(c, m - 1)
+    return c[:, 0] + (c[:, 1] + c[:, 2] * m) * m
+
+
+def cell_lists(keys, m):
+    """Sort by key (stable) and return (order, start) with start[c]..start[c+1]
+    the sorted positions of the particles in cell c (Sec. 4, sorting)."""
+    order = np.argsort(keys, kind="stable")
+    start = np.searchsorted(keys[order], np.arange(m ** 3 + 1))
+    return order, start
+
+
+# --- Sec. 2.1 / 3.1 / 3.4: grid operators ----------------------------------
+
+def _window(Yc, dx, M_G, M):
+    """Support of one coordinate: grid indices (mod M) and displacements d."""
+    start = np.floor(Yc / dx - M_G / 2.0).astype(np.int64) + 1
+    j = start[:, None] + np.arange(M_G)[None, :]
+    d = j * dx - Yc[:, None]
+    return np.mod(j, M), d
+
+
+def _particle_weights(p, Yw):
+    """For a block of particles: flat grid indices and, at every support point,
+    the modified force kernel Delta~(d; Sigma) (Sec. 3, definition of Delta~)
+    and the torque factor Delta(d; Sigma_D) / (2 Sigma_D^2) with d itself."""
+    M, MG = p.M, p.M_G
+    ix, dxs = _window(Yw[:, 0], p.dx, MG, M)
+    iy, dys = _window(Yw[:, 1], p.dx, MG, M)
+    iz, dzs = _window(Yw[:, 2], p.dx, MG, M)
+    # full 3-D support, shape (n, MG, MG, MG), axis order (x, y, z)
+    flat = (ix[:, :, None, None] * M + iy[:, None, :, None]) * M + iz[:, None, None, :]
+    dx3 = np.broadcast_to(dxs[:, :, None, None], flat.shape)
+    dy3 = np.broadcast_to(dys[:, None, :, None], flat.shape)
+    dz3 = np.broadcast_to(dzs[:, None, None, :], flat.shape)
+    r2 = dx3 ** 2 + dy3 ** 2 + dz3 ** 2
+    S2 = p.Sigma ** 2
+    # Delta~ = (1 + (sigma^2 - Sigma^2)/2 lap) Delta(.; Sigma); lap Delta = Delta (r^2/S^4 - 3/S^2)
+    dmod = cf.gaussian(np.sqrt(r2), p.Sigma) * (1.0 + 0.5 * (p.sigma ** 2 - S2) * (r2 / S2 ** 2 - 3.0 / S2))
+    # -(1/2) T x grad Delta(.; Sigma_D) = (1 / 2 Sigma_D^2) Delta (T x d)
+    dtor = cf.gaussian(np.sqrt(r2), p.Sigma_D) / (2.0 * p.Sigma_D ** 2)
+    return flat, dmod, dtor, (dx3, dy3, dz3)
+
+
+def spread(p, Y, F, T=None, chunk=2048):
+    """J~^dagger[F] + N~^dagger[T] on the grid (Sec. 3.1 eq. force_kernel_mod,
+    Sec. 3.4 eq. torque_kernel_mod), truncated to M_G^3 points (Sec. 2.1).
+
+    Returns f with shape (3, M, M, M), axes (component, x, y, z).
+    """
+    Yw = wrap(Y, p.L)
+    F = np.asarray(F, dtype=np.float64)
+    M3 = p.M ** 3
+    f = np.zeros((3, M3))
+    for lo in range(0, len(Yw), chunk):
+        hi = min(lo + chunk, len(Yw))
+        flat, dmod, dtor, (dx3, dy3, dz3) = _particle_weights(p, Yw[lo:hi])
+        idx = flat.ravel()
+        Fc = F[lo:hi]
+        comps = [dmod * Fc[:, c, None, None, None] for c in range(3)]
+        if T is not None:
+            Tc = np.asarray(T, dtype=np.float64)[lo:hi]
+            t = [Tc[:, c, None, None, None] for c in range(3)]
+            # T x d
+            comps[0] = comps[0] + dtor * (t[1] * dz3 - t[2] * dy3)
+            comps[1] = comps[1] + dtor * (t[2] * dx3 - t[0] * dz3)
+            comps[2] = comps[2] + dtor * (t[0] * dy3 - t[1] * dx3)
+        for c in range(3):
+            f[c] += np.bincount(idx, weights=comps[c].ravel(), minlength=M3)
+    return f.reshape(3, p.M, p.M, p.M)
+
+
+def wavenumbers(p):
+    """Wavenumbers 2 pi j / L of numpy's FFT ordering, per axis."""
+    return 2.0 * np.pi * np.fft.fftfreq(p.M, d=1.0 / p.M) / p.L
+
+
+def stokes_solve(p, f):
+    """Inverse Stokes operator L^{-1} in Fourier space (Sec. 2.1 step 2,
+    App. A): u^ = (I - k k^T / k^2) f^ / (eta k^2), u^(0) = 0.
+
+    Input and output have shape (3, M, M, M).  For even M the modes with
+    index M/2 on any axis are zeroed.
+    """
+    M = p.M
+    fh = np.fft.fftn(f, axes=(1, 2, 3))
+    k = wavenumbers(p)
+    kx = k[:, None, None]
+    ky = k[None, :, None]
+    kz = k[None, None, :]
+    k2 = kx ** 2 + ky ** 2 + kz ** 2
+    k2s = np.where(k2 == 0.0, 1.0, k2)
+    kdotf = (kx * fh[0] + ky * fh[1] + kz * fh[2]) / k2s
+    uh = np.empty_like(fh)
+    uh[0] = (fh[0] - kx * kdotf) / (p.eta * k2s)
+    uh[1] = (fh[1] - ky * kdotf) / (p.eta * k2s)
+    uh[2] = (fh[2] - kz * kdotf) / (p.eta * k2s)
+    uh[:, 0, 0, 0] = 0.0
+    if M % 2 == 0:
+        h = M // 2
+        uh[:, h, :, :] = 0.0
+        uh[:, :, h, :] = 0.0
+        uh[:, :, :, h] = 0.0
+    return np.real(np.fft.ifftn(uh, axes=(1, 2, 3)))
+
+
+def interp(p, Y, u, want_omega=True, chunk=2048):
+    """J~[u] and N~[u] (Sec. 3.1 eq. avg_particle_vel_mod, Sec. 3.4
+    eq. avg_particle_rot_mod) by the trapezoid rule on the M_G^3 support
+    (Sec. 2.1 step 3):
+
+    V_m     = dV sum_g u_g Delta~(x_g - Y_m; Sigma)
+    Omega_m = dV sum_g Delta(x_g - Y_m; Sigma_D) (x_g - Y_m) x u_g / (2 Sigma_D^2)
+
+    (the second is (1/2) int (curl u) Delta after integration by parts).
+    """
+    Yw = wrap(Y, p.L)
+    uf = u.reshape(3, -1)
+    dV = p.dx ** 3
+    V = np.zeros((len(Yw), 3))
+    W = np.zeros((len(Yw), 3))
+    for lo in range(0, len(Yw), chunk):
+        hi = min(lo + chunk, len(Yw))
+        flat, dmod, dtor, (dx3, dy3, dz3) = _particle_weights(p, Yw[lo:hi])
+        ug = [uf[c][flat] for c in range(3)]
+        ax = (1, 2, 3)
+        for c in range(3):
+            V[lo:hi, c] = dV * np.sum(dmod * ug[c], axis=ax)
+        if want_omega:
+            W[lo:hi, 0] = dV * np.sum(dtor * (dy3 * ug[2] - dz3 * ug[1]), axis=ax)
+            W[lo:hi, 1] = dV * np.sum(dtor * (dz3 * ug[0] - dx3 * ug[2]), axis=ax)
+            W[lo:hi, 2] = dV * np.sum(dtor * (dx3 * ug[1] - dy3 * ug[0]), axis=ax)
+    return V, W
+
+
+# --- Sec. 4 step 6: pairwise correction, App. B: self correction -----------
+
+def min_image(x, L):
+    return x - L * np.round(x / L)
+
+
+def pair_correction(p, Y, F, T=None, targets=None):
+    """Velocity and angular-velocity corrections (M - M~)(F; T) for pairs with
+    R_mn < R_c found through the cell lists (Sec. 4, pairwise correction),
+    plus the self corrections of App. B.
+
+    targets: indices of the particles whose corrections are wanted (default
+    all).  Returns dV, dW of shape (len(targets), 3).
+    """
+    Yw = wrap(Y, p.L)
+    N = len(Yw)
+    F = np.asarray(F, dtype=np.float64)
+    Tq = np.zeros((N, 3)) if T is None else np.asarray(T, dtype=np.float64)
+    if targets is None:
+        targets = np.arange(N)
+    dV = np.zeros((len(targets), 3))
+    dW = np.zeros((len(targets), 3))
+    sg, sD, Sg, SD, eta = p.sigma, p.sigma_D, p.Sigma, p.Sigma_D, p.eta
+    if p.R_c > 0.0:
+        m = cell_counts(p.L, p.R_c)
+        keys = hash_particles(Yw, p.L, m)
+        order, start = cell_lists(keys, m)
+        cw = p.L / m
+    for t, n in enumerate(targets):
+        if p.R_c <= 0.0:
+            dV[t] += cf.self_correction_VF(p.a, sg, Sg, eta) * F[n]
+            dW[t] += cf.self_correction_OT(p.a, SD, eta) * Tq[n]
+            continue
+        c = np.minimum(np.floor(Yw[n] / cw).astype(np.int64), m - 1)
+        cand = []
+        for oz in (-1, 0, 1):
+            for oy in (-1, 0, 1):
+                for ox in (-1, 0, 1):
+                    cx, cy, cz = (c[0] + ox) % m, (c[1] + oy) % m, (c[2] + oz) % m
+                    key = cx + (cy + cz * m) * m
+                    cand.append(order[start[key]:start[key + 1]])
+        cand = np.concatenate(cand)
+        cand = cand[cand != n]
+        x = min_image(Yw[n][None, :] - Yw[cand], p.L)
+        r = np.sqrt(np.sum(x * x, axis=1))
+        sel = r < p.R_c
+        cand, x = cand[sel], x[sel]
+        if len(cand):
+            CVF = cf.correction_VF(x, sg, Sg, eta)
+            CVT = cf.correction_VT(x, sg, sD, Sg, SD, eta)
+            COF = cf.correction_OF(x, sg, sD, Sg, SD, eta)
+            COT = cf.correction_OT(x, sD, SD, eta)
+            dV[t] = np.einsum("pij,pj->i", CVF, F[cand]) + np.einsum("pij,pj->i", CVT, Tq[cand])
+            dW[t] = np.einsum("pij,pj->i", COF, F[cand]) + np.einsum("pij,pj->i", COT, Tq[cand])
+        dV[t] += cf.self_correction_VF(p.a, sg, Sg, eta) * F[n]
+        dW[t] += cf.self_correction_OT(p.a, SD, eta) * Tq[n]
+    return dV, dW
+
+
+def mobility(p, Y, F, T=None, targets=None, with_correction=True):
+    """Fast-FCM action of the mobility (Sec. 4): (V, Omega) = M~ (F, T) + (M - M~)(F, T).
+
+    Spreading always uses every particle; interpolation and correction are
+    evaluated for ``targets`` (default all), in that order.
+    """
+    Y = np.asarray(Y, dtype=np.float64)
+    N = len(Y)
+    if targets is None:
+        targets = np.arange(N)
+    f = spread(p, Y, F, T)
+    u = stokes_solve(p, f)
+    V, W = interp(p, Y[targets], u)
+    if with_correction:
+        dV, dW = pair_correction(p, Y, F, T, targets)
+        V = V + dV
+        W = W + dW
+    return V, W
