@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Throughput of the fast-FCM mobility on one MI355X.
+
+A step is one fcm_mobility call (sort, spread, FFT Stokes solve, interpolation,
+FP64 pair correction) on the dense suspension: N = 100,000 spheres (a = 1) at
+volume fraction 10 %, 256^3 grid, Sigma = dx, M_G = 10, R_c = 5.5 Sigma, with
+inputs resident in device memory.  The value is particle-mobility evaluations
+per second (N / seconds per step) of the FP32-bulk path; the FP64 path, call
+latency percentiles, per-stage times, the roofline of the dominant kernel and
+the oracle timed on host cores are reported beside it on the same JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload dense|dilute|rods|small]
+                    [--no-cpu] [--no-fp64]
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {"small": 0, "dilute": 1, "dense": 2, "rods": 3}
+HBM_PEAK_GBS = 8000.0
+METRIC = "mobility evals/s (N=1e5, ≤1e-4 rel err) FP32 vs FP64; p50/p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="dense", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 path")
+    ap.add_argument("--cpu-sample", type=int, default=1000)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(w, stage):
+    """Bytes one launch of `stage` must move (FP32 bulk): a field is 3 M^3 floats."""
+    M, N = w["grid"], w["N"]
+    field = 12 * M ** 3
+    rec = 48 * N                   # s[3], f[3], F[3], T[3] at 4 bytes
+    return {"spread": field + rec, "fft_x_fwd": 2 * field, "fft_y_fwd": 2 * field,
+            "fft_z_solve": 2 * field, "fft_y_inv": 2 * field, "fft_x_inv": 2 * field,
+            "interp": field + rec + 48 * N}.get(stage)
+
+
+KERNEL_OF_STAGE = {"spread": "k_spread", "fft_x_fwd": "k_fft_x_r2c", "fft_y_fwd": "k_fft_y",
+                   "fft_z_solve": "k_fft_z_solve", "fft_y_inv": "k_fft_y", "fft_x_inv": "k_fft_x_c2r",
+                   "interp": "k_interp", "pair": "k_pair", "sort": "k_hash"}
+SOURCE_OF_STAGE = {"spread": "fcm_grid.hip", "interp": "fcm_grid.hip", "pair": "fcm_pair.hip",
+                   "sort": "fcm_sort.hip"}
+
+
+def traffic_for(stage, workload):
+    """HBM bytes per launch from the committed counter summary of this kernel and
+    workload, or None when absent or taken on a different kernel source."""
+    src = SOURCE_OF_STAGE.get(stage, "fcm_fft.hip")
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_2310_12651_amd", "csrc", src), "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != h:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_path(plan, args, Y, F, T, V, W, torch):
+    """Warm up, then time exactly args.steps calls; per-call events give latency."""
+    st = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.mobility(Y, F, T, V, W)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(st)
+    for k in range(args.steps):
+        plan.mobility(Y, F, T, V, W)
+        evs[k + 1].record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps))
+    total_ms = evs[0].elapsed_time(evs[-1])
+    stages, ncalls = plan.stage_times()
+    plan.set_timing(False)
+    q = lambda p: lat[min(len(lat) - 1, int(math.ceil(p * len(lat))) - 1)]
+    return dict(ms_per_step=total_ms / args.steps, wall_s=wall, p50_ms=q(0.50), p99_ms=q(0.99),
+                stages_ms={k: v / max(ncalls, 1) for k, v in stages.items()})
+
+
+def cpu_baseline(w, n_sample, V_gpu, W_gpu):
+    """The oracle (plain FP64 numpy) on a bounded sample of the same workload:
+    spreading of all N particles and the full FFT solve are timed as they are;
+    interpolation and pair correction are timed on a seeded subsample and scaled
+    to N.  Also returns the GPU error against the oracle on the subsample."""
+    import numpy as np
+    from oracle import fastfcm as ff
+    p = ff.Params(L=w["L"], M=w["grid"], a=w["a"], Sigma=w["Sigma"], M_G=w["M_G"], R_c=w["R_c"])
+    N = w["N"]
+    rng = np.random.default_rng(12345)
+    sub = np.sort(rng.choice(N, size=min(n_sample, N), replace=False))
+    t0 = time.perf_counter()
+    f = ff.spread(p, w["Y"], w["F"], w["T"])
+    t1 = time.perf_counter()
+    u = ff.stokes_solve(p, f)
+    t2 = time.perf_counter()
+    V, W = ff.interp(p, w["Y"][sub], u)
+    t3 = time.perf_counter()
+    dV, dW = ff.pair_correction(p, w["Y"], w["F"], w["T"], targets=sub)
+    t4 = time.perf_counter()
+    scale = N / len(sub)
+    est = (t1 - t0) + (t2 - t1) + scale * ((t3 - t2) + (t4 - t3))
+    Vo, Wo = V + dV, W + dW
+    err = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    epsm = lambda a, b: float(np.mean(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)))
+    acc = dict(relV=err(V_gpu[sub], Vo), relW=err(W_gpu[sub], Wo), epsV=epsm(V_gpu[sub], Vo),
+               epsW=epsm(W_gpu[sub], Wo), n=len(sub))
+    base = dict(value=N / est, unit="evals/s", cores=1, kind="oracle",
+                sample=(f"numpy FP64 oracle, single thread: spread of all {N} particles "
+                        f"({t1 - t0:.1f} s) and the {w['grid']}^3 FFT solve ({t2 - t1:.1f} s) timed in "
+                        f"full; interpolation ({t3 - t2:.2f} s) and pair correction ({t4 - t3:.2f} s) "
+                        f"timed on {len(sub)} seeded particles and scaled by {scale:.0f}"))
+    return base, acc
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the fast-FCM path here runs on a single device "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2310_12651_amd import FCM_FP32_BULK, FCM_FP64, Plan
+
+    wid = WORKLOADS[args.workload]
+    t = time.perf_counter()
+    w = workloads.workload(wid)
+    log(f"[bench] workload {w['name']} drawn in {time.perf_counter() - t:.1f} s")
+    dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    Y, F, T = dev(w["Y"]), dev(w["F"]), dev(w["T"])
+    N = w["N"]
+    V = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+    W = torch.empty_like(V)
+    mk = lambda prec: Plan(N, w["L"], w["a"], w["Sigma"], w["grid"], w["R_c"], support=w["M_G"],
+                           precision=prec)
+    plan32 = mk(FCM_FP32_BULK)
+    r32 = time_path(plan32, args, Y, F, T, V, W, torch)
+    log(f"[bench] fp32 {r32['ms_per_step']:.3f} ms/step  stages {r32['stages_ms']}")
+    V32, W32 = V.cpu().numpy(), W.cpu().numpy()
+    r64 = None
+    acc64 = None
+    if not args.no_fp64:
+        plan32.close()
+        plan64 = mk(FCM_FP64)
+        r64 = time_path(plan64, args, Y, F, T, V, W, torch)
+        log(f"[bench] fp64 {r64['ms_per_step']:.3f} ms/step  stages {r64['stages_ms']}")
+        V64, W64 = V.cpu().numpy(), W.cpu().numpy()
+        acc64 = dict(relV_fp32_vs_fp64=float(np.linalg.norm(V32 - V64) / np.linalg.norm(V64)),
+                     relW_fp32_vs_fp64=float(np.linalg.norm(W32 - W64) / np.linalg.norm(W64)))
+        plan64.close()
+    stages = {k: v for k, v in r32["stages_ms"].items()}
+    dom = max(stages, key=stages.get)
+    roof = None
+    grid_stages = [s for s in stages if algorithmic_bytes(w, s)]
+    if grid_stages:
+        dom_grid = dom if dom in grid_stages else max(grid_stages, key=stages.get)
+        ab = algorithmic_bytes(w, dom_grid)
+        ach = ab / (stages[dom_grid] * 1e-3) / 1e9
+        tr = traffic_for(dom_grid, args.workload)
+        roof = dict(kernel=KERNEL_OF_STAGE[dom_grid], bound="hbm", achieved=round(ach, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
+                    traffic=tr, algorithmic_bytes=ab, launch_ms=round(stages[dom_grid], 5))
+    per_stage_gbs = {s: round(algorithmic_bytes(w, s) / (stages[s] * 1e-3) / 1e9, 1)
+                     for s in grid_stages}
+    base, acc = None, None
+    if not args.no_cpu:
+        log("[bench] timing the oracle on the host (bounded sample)")
+        base, acc = cpu_baseline(w, args.cpu_sample, V32, W32)
+        log(f"[bench] oracle {base['value']:.3g} evals/s; accuracy {acc}")
+    out = {
+        "metric": METRIC,
+        "value": N / (r32["ms_per_step"] * 1e-3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 grid + f64 pair",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "N": N, "grid": w["grid"], "Sigma": w["Sigma"],
+                   "M_G": w["M_G"], "R_c": w["R_c"], "L": w["L"], "parallelism": "single GPU"},
+        "latency_ms": {"p50": r32["p50_ms"], "p99": r32["p99_ms"]},
+        "stages_ms": {k: round(v, 5) for k, v in stages.items()},
+        "stage_gbs": per_stage_gbs,
+        "fp64": None if r64 is None else {"value": N / (r64["ms_per_step"] * 1e-3),
+                                           "ms_per_step": r64["ms_per_step"],
+                                           "latency_ms": {"p50": r64["p50_ms"], "p99": r64["p99_ms"]},
+                                           "stages_ms": {k: round(v, 5) for k, v in r64["stages_ms"].items()}},
+        "accuracy": {"vs_oracle_subsample": acc, "fp32_vs_fp64": acc64},
+        "roofline": roof,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

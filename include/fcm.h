@@ -1,0 +1,153 @@
+/*
+ * fcm.h -- C ABI of the fast force-coupling-method (fast FCM) mobility library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Fast FCM (Su & Keaveny, arXiv 2310.12651) applies the periodic FCM mobility
+ * of N spheres of radius a: given positions Y_n, forces F_n and torques T_n in
+ * the triply periodic box [0, L)^3 with viscosity eta, it returns the particle
+ * velocities V_n and angular velocities Omega_n (Sec. 2, Sec. 3.4, eq.
+ * symmetric_FFT_mod).  It spreads F and T onto a grid with kernels of the
+ * widened width Sigma (Sec. 3, modified kernel Delta~; Sec. 3.4, eq.
+ * torque_kernel_mod), solves Stokes flow in Fourier space (Sec. 2.1),
+ * interpolates back (Sec. 3.1, eq. avg_particle_vel_mod; Sec. 3.4,
+ * eq. avg_particle_rot_mod), and adds the pairwise correction M - M~ for pairs
+ * closer than R_c plus the self correction (Sec. 3.2 eq. correction_VF,
+ * Sec. 3.4 eqs. correction_WF and correction_WT, App. B), following the steps
+ * of Sec. 4.
+ *
+ * Conventions (all calls):
+ *  - Every call returns an int status: FCM_OK (0) or a negative FCM_E* code.
+ *    No C++ exception crosses this interface.
+ *  - Particle arrays are DEVICE pointers to N x 3 row-major FP64 values
+ *    (x, y, z interleaved per particle) on the device the plan was created on.
+ *    The caller owns them.  Outputs are written in the caller's particle order.
+ *  - Positions may lie anywhere; they are wrapped into [0, L).  Non-finite
+ *    positions (and ones too large to wrap) are replaced by 0 and reported
+ *    by fcm_plan_last_error().
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *    and return without waiting; results are ready when the stream reaches
+ *    them.  A plan owns scratch buffers, so concurrent calls on one plan race:
+ *    use one plan per concurrently used stream.
+ *  - Grid fields exchanged by the stage calls are DEVICE buffers of
+ *    3 * grid^3 values in the plan's grid precision (double for FCM_FP64,
+ *    float for FCM_FP32_BULK), component-major, x fastest:
+ *    field[c * grid^3 + i + grid * (j + grid * k)] is component c at the grid
+ *    point (i, j, k) * L / grid.
+ *  - Units: mobilities scale as 1/eta (default eta = 1).
+ */
+#ifndef FCM_H
+#define FCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcm_plan_impl* fcm_plan_t;
+
+enum {
+    FCM_OK = 0,
+    FCM_EINVAL = -1,      /* an argument is out of its documented range            */
+    FCM_ENOMEM = -2,      /* device or host allocation failed                      */
+    FCM_EDEVICE = -3,     /* a HIP runtime call failed                             */
+    FCM_ERANGE = -4,      /* r_cut >= L/2: pairs would need more than one image    */
+    FCM_ENONFINITE = -5   /* non-finite input seen by the last call (see below)    */
+};
+
+/* Precision of the grid part (spreading, FFT Stokes solve, interpolation).
+ * The pair correction and the final V, Omega are FP64 in both modes. */
+enum { FCM_FP64 = 0, FCM_FP32_BULK = 1 };
+
+typedef struct {
+    double eta;          /* viscosity; default 1                                        */
+    int support;         /* M_G, grid points per direction of a kernel's support
+                            (Sec. 2.1); 0 = smallest even >= 10 Sigma/dx, at least 8    */
+    double sigma_D_grid; /* Sigma_D, width of the torque kernel on the grid (Sec. 3.4);
+                            0 = Sigma, the paper's choice                                */
+    int precision;       /* FCM_FP64 or FCM_FP32_BULK (default)                          */
+    int kahan;           /* 1 = compensated sums in FP32 spreading (default 1)           */
+} fcm_options;
+
+/* Fill `opt` with the defaults listed above. */
+int fcm_options_default(fcm_options* opt);
+
+/*
+ * Create a plan for N particles of radius a in the periodic cube [0, L)^3.
+ *   sigma_delta : Sigma, width of the modified Gaussian (Sec. 3); Sigma >= sigma
+ *                 = a / sqrt(pi).  Sigma == sigma is standard FCM (no correction).
+ *   grid        : grid points per axis, an even 2^p 3^q between 8 and 1024
+ *                 (dx = L / grid).
+ *   r_cut       : R_c, pair-correction cut-off (Sec. 4); 0 <= R_c < L/2.
+ * Allocates every device buffer the plan needs on the current HIP device;
+ * later calls allocate nothing.
+ * Errors: FCM_EINVAL if N <= 0, L <= 0, a <= 0, Sigma < sigma, the grid is not
+ * an even 2^p 3^q in range, or the support exceeds the grid, 32, or (FP64) 24;
+ * FCM_ERANGE if
+ * r_cut >= L/2; FCM_ENOMEM / FCM_EDEVICE on allocation or runtime failure.
+ */
+int fcm_plan(fcm_plan_t* out, int64_t N, double L, double a, double sigma_delta,
+             int grid, double r_cut);
+/* As fcm_plan with options (NULL = defaults). */
+int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_delta,
+                int grid, double r_cut, const fcm_options* opt);
+/* Release a plan and its device buffers (synchronises the device first). */
+int fcm_plan_destroy(fcm_plan_t p);
+
+/*
+ * The mobility (Sec. 4, all steps): V, Omega = M (F, T).
+ *   pos, F : device, N x 3 FP64.   T : device N x 3 FP64 or NULL (zero torques).
+ *   V      : device, N x 3 FP64, overwritten.
+ *   Omega  : device, N x 3 FP64, overwritten; or NULL to skip angular velocities.
+ */
+int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double* T,
+                 double* V, double* Omega, void* stream);
+
+/* Stage calls: the operators of Sec. 2.1 / 3.1 / 3.4 one at a time. */
+
+/* grid_out = J~^dagger[F] + N~^dagger[T] on the grid (modified force kernel of
+ * width Sigma, torque kernel of width Sigma_D, each truncated to M_G^3 points). */
+int fcm_spread(fcm_plan_t p, const double* pos, const double* F, const double* T,
+               void* grid_out, void* stream);
+/* In place: field -> L^{-1} field, the Fourier Stokes solve (Sec. 2.1 step 2,
+ * App. A): u^ = (I - k k^T/k^2) f^ / (eta k^2), u^(0) = 0, and every Fourier mode
+ * with index grid/2 along any axis set to 0. */
+int fcm_solve(fcm_plan_t p, void* grid_inout, void* stream);
+/* V = J~[u], Omega = N~[u] by the trapezoid rule on each particle's support
+ * (Omega may be NULL).  V and Omega are overwritten. */
+int fcm_interp(fcm_plan_t p, const double* pos, const void* grid_in,
+               double* V, double* Omega, void* stream);
+/* Adds the pairwise corrections (M - M~)(F, T) for pairs with |Y_n - Y_m| < R_c
+ * (minimum image) and the self corrections of App. B into V and Omega. */
+int fcm_correct(fcm_plan_t p, const double* pos, const double* F, const double* T,
+                double* V, double* Omega, void* stream);
+
+/* Plan properties. */
+int fcm_plan_info(fcm_plan_t p, int64_t* N, int* grid, int* support, int* precision,
+                  int* cells_per_axis);
+/* Device bytes a plan with these sizes would allocate (for admission control). */
+int fcm_plan_footprint(int64_t N, int grid, int precision, int64_t* bytes);
+/* Synchronises the last call's stream and returns FCM_ENONFINITE if that call saw a
+ * non-finite position, else FCM_OK; clears the flag. */
+int fcm_plan_last_error(fcm_plan_t p);
+/*
+ * Per-stage timing with HIP events recorded on the call's stream.  When enabled,
+ * every fcm_mobility call records FCM_NUM_STAGES + 1 events (up to 4096 calls are
+ * kept); fcm_plan_stage_times synchronises, adds the elapsed milliseconds of each
+ * stage over the recorded calls into ms_out[0..FCM_NUM_STAGES), stores the number
+ * of calls in *ncalls, and clears the record.  Stages, in order: sort (hash, scan,
+ * scatter, record gather), spread, FFT x forward, FFT y forward, FFT z + projection,
+ * FFT y inverse, FFT x inverse, interpolation, pair correction (gather + pairs).
+ */
+#define FCM_NUM_STAGES 9
+int fcm_plan_set_timing(fcm_plan_t p, int enable);
+int fcm_plan_stage_times(fcm_plan_t p, double* ms_out, int* ncalls);
+
+/* Static description of a status code. */
+const char* fcm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCM_H */

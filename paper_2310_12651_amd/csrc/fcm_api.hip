@@ -1,0 +1,510 @@
+// Public C ABI of the fast-FCM library (include/fcm.h): plan construction,
+// validation, and the orchestration of the hot path on one HIP stream:
+//   hash -> sort -> spread -> Stokes solve (5 FFT passes) -> interpolate ->
+//   pair correction (Sec. 4, steps 1-6).
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "fcm_internal.h"
+
+namespace fcm {
+int fft_maxe(int precision, bool zpass);
+}
+
+using namespace fcm;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+bool is_smooth_even(int n) {
+    if (n < 8 || n > kMaxGrid || (n & 1)) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+// radices (8, 4, 2 for the power of two; 3 for each factor 3), largest first
+RadixPlan make_radix_plan(int n) {
+    RadixPlan rp;
+    rp.n = n;
+    rp.nst = 0;
+    int m = n;
+    int p2 = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++p2;
+    }
+    while (p2 >= 3) {
+        rp.rad[rp.nst++] = 8;
+        p2 -= 3;
+    }
+    if (p2 == 2) rp.rad[rp.nst++] = 4;
+    if (p2 == 1) rp.rad[rp.nst++] = 2;
+    while (m % 3 == 0) {
+        rp.rad[rp.nst++] = 3;
+        m /= 3;
+    }
+    return rp;
+}
+
+int pow2_floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+void choose_tiles(fcm_plan_impl* P) {
+    const int M = P->M, MG = P->MG;
+    double best = 1e300;
+    int bx = 2, by = 2;
+    for (int tx = 2; tx <= 64; ++tx) {
+        if (M % tx) continue;
+        for (int ty = 2; tx * ty <= 64; ++ty) {
+            if (M % ty) continue;
+            // candidate-scan work per grid point of a wavefront tile
+            const double score = (double)(tx + MG - 1) * (ty + MG - 1) / (tx * ty) +
+                                 (tx < 8 ? 0.01 : 0.0);
+            if (score < best - 1e-12) {
+                best = score;
+                bx = tx;
+                by = ty;
+            }
+        }
+    }
+    P->TX = bx;
+    P->TY = by;
+    const int tzs[] = {16, 12, 8, 6, 4, 2};
+    P->TZ = 2;
+    for (int t : tzs)
+        if (M % t == 0) {
+            P->TZ = t;
+            break;
+        }
+    P->nbx = M / P->TX;
+    P->nby = M / P->TY;
+    P->nbz = M / P->TZ;
+    P->nbins = P->nbx * P->nby * P->nbz;
+    auto back = [&](int T, int nb) {
+        int b = (MG - 1 + T - 1) / T;
+        return b > nb - 1 ? nb - 1 : b;
+    };
+    P->backx = back(P->TX, P->nbx);
+    P->backy = back(P->TY, P->nby);
+    P->backz = back(P->TZ, P->nbz);
+}
+
+size_t real_size(int precision) { return precision == FCM_FP64 ? sizeof(double) : sizeof(float); }
+
+size_t grid_rec_size(int precision) {
+    return precision == FCM_FP64 ? sizeof(GridRec<double>) : sizeof(GridRec<float>);
+}
+
+constexpr int kMaxTimedCalls = 1024;
+constexpr int kEvPerCall = FCM_NUM_STAGES + 1;
+
+void free_events(fcm_plan_impl* P) {
+    if (!P->events) return;
+    for (int i = 0; i < P->ev_cap * kEvPerCall; ++i)
+        if (P->events[i]) (void)hipEventDestroy(P->events[i]);
+    free(P->events);
+    P->events = nullptr;
+    P->ev_cap = 0;
+    P->ev_calls = 0;
+}
+
+// the event set of the current call, or NULL when not timing / record full
+hipEvent_t* call_events(fcm_plan_impl* P) {
+    if (!P->timing || P->ev_calls >= P->ev_cap) return nullptr;
+    return P->events + (size_t)(P->ev_calls++) * kEvPerCall;
+}
+
+void free_plan(fcm_plan_impl* P) {
+    if (!P) return;
+    free_events(P);
+    void* bufs[] = {P->grid, P->twid, P->counts, P->starts, P->keys, P->ranks,
+                    P->perm, P->scan_tmp, P->grec, P->prec, P->flag};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete P;
+}
+
+int map_err(hipError_t e) {
+    if (e == hipSuccess) return FCM_OK;
+    if (e == hipErrorOutOfMemory) return FCM_ENOMEM;
+    return FCM_EDEVICE;
+}
+
+hipError_t sort_particles(fcm_plan_impl* P, const double* pos, hipStream_t st) {
+    hipError_t e;
+    if ((e = launch_fill(P->counts, P->nbins + P->ncells, 0, st)) != hipSuccess) return e;
+    if ((e = launch_hash(P, pos, st)) != hipSuccess) return e;
+    if ((e = launch_scan(P->counts, P->starts, P->nbins, P->scan_tmp, st)) != hipSuccess) return e;
+    if ((e = launch_scan(P->counts + P->nbins, P->starts + P->nbins + 1, P->ncells, P->scan_tmp,
+                         st)) != hipSuccess)
+        return e;
+    return launch_scatter(P, st);
+}
+
+bool needs_correction(const fcm_plan_impl* P) {
+    return !(P->Sigma == P->sigma && P->SigmaD == P->sigmaD);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fcm_options_default(fcm_options* opt) {
+    if (!opt) return FCM_EINVAL;
+    opt->eta = 1.0;
+    opt->support = 0;
+    opt->sigma_D_grid = 0.0;
+    opt->precision = FCM_FP32_BULK;
+    opt->kahan = 1;
+    return FCM_OK;
+}
+
+int fcm_plan_footprint(int64_t N, int grid, int precision, int64_t* bytes) {
+    if (!bytes || N <= 0 || grid <= 0) return FCM_EINVAL;
+    const int64_t M = grid;
+    const int64_t rs = (int64_t)real_size(precision);
+    int64_t b = 3 * M * M * M * rs;                     // field / spectrum
+    b += M * 2 * rs;                                    // twiddles
+    b += 6 * N * (int64_t)sizeof(int);                  // keys, ranks, perm
+    b += N * (int64_t)(grid_rec_size(precision) + sizeof(PairRec));
+    const int64_t nbins_max = (M / 2) * (M / 2) * (M / 2);
+    const int64_t cells = (int64_t)kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis;
+    b += 2 * (nbins_max + 1) * (int64_t)sizeof(int) + 2 * (cells + 1) * (int64_t)sizeof(int);
+    b += 4096 * (int64_t)sizeof(int);
+    *bytes = b;
+    return FCM_OK;
+}
+
+int fcm_plan(fcm_plan_t* out, int64_t N, double L, double a, double sigma_delta, int grid,
+             double r_cut) {
+    return fcm_plan_ex(out, N, L, a, sigma_delta, grid, r_cut, nullptr);
+}
+
+int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_delta, int grid,
+                double r_cut, const fcm_options* opt_in) {
+    if (!out) return FCM_EINVAL;
+    *out = nullptr;
+    fcm_options opt;
+    fcm_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    if (N <= 0 || N > (int64_t)1 << 29) return FCM_EINVAL;
+    if (!(L > 0.0) || !isfinite(L) || !(a > 0.0) || !isfinite(a)) return FCM_EINVAL;
+    if (!(opt.eta > 0.0) || !isfinite(opt.eta)) return FCM_EINVAL;
+    if (opt.precision != FCM_FP64 && opt.precision != FCM_FP32_BULK) return FCM_EINVAL;
+    if (!is_smooth_even(grid)) return FCM_EINVAL;
+    const double sigma = a / sqrt(kPi);
+    const double sigmaD = a / cbrt(6.0 * sqrt(kPi));
+    if (!(sigma_delta >= sigma * (1.0 - 1e-12)) || !isfinite(sigma_delta)) return FCM_EINVAL;
+    const double Sigma = sigma_delta < sigma ? sigma : sigma_delta;
+    double SigmaD = opt.sigma_D_grid > 0.0 ? opt.sigma_D_grid : Sigma;
+    if (!(SigmaD >= sigmaD * (1.0 - 1e-12)) || !isfinite(SigmaD)) return FCM_EINVAL;
+    if (SigmaD < sigmaD) SigmaD = sigmaD;
+    if (!(r_cut >= 0.0) || !isfinite(r_cut)) return FCM_EINVAL;
+    if (r_cut >= 0.5 * L) return FCM_ERANGE;
+    const double dx = L / grid;
+    int MG = opt.support;
+    if (MG == 0) {
+        const double wmax = Sigma > SigmaD ? Sigma : SigmaD;
+        MG = (int)ceil(10.0 * wmax / dx - 1e-9);
+        if (MG & 1) ++MG;
+        if (MG < 8) MG = 8;
+    }
+    if (MG < 2 || MG > kMaxSupport || MG > grid) return FCM_EINVAL;
+    // the FP64 spreading stages 64 particles with M_G-point tables in 64 KB of LDS
+    if (opt.precision == FCM_FP64 && MG > 24) return FCM_EINVAL;
+
+    fcm_plan_impl* P = new (std::nothrow) fcm_plan_impl;
+    if (!P) return FCM_ENOMEM;
+    memset(P, 0, sizeof(*P));
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return FCM_EDEVICE;
+    }
+    P->N = N;
+    P->L = L;
+    P->a = a;
+    P->eta = opt.eta;
+    P->sigma = sigma;
+    P->sigmaD = sigmaD;
+    P->Sigma = Sigma;
+    P->SigmaD = SigmaD;
+    P->rc = r_cut;
+    P->dx = dx;
+    P->M = grid;
+    P->H = grid / 2;
+    P->MG = MG;
+    P->precision = opt.precision;
+    P->kahan = opt.kahan ? 1 : 0;
+    choose_tiles(P);
+    int m = 3;
+    if (r_cut > 0.0) {
+        const double q = L / r_cut;
+        m = q > (double)kMaxCellsPerAxis ? kMaxCellsPerAxis : (int)q;
+        if (m < 3) m = 3;
+    }
+    P->m = m;
+    P->ncells = m * m * m;
+    P->radM = make_radix_plan(grid);
+    P->radH = make_radix_plan(grid / 2);
+    const int mxy = fft_maxe(P->precision, false) * 256;
+    const int mz = fft_maxe(P->precision, true) * 256;
+    if (grid > mz) {
+        delete P;
+        return FCM_EINVAL;
+    }
+    P->Wy = pow2_floor(mxy / grid);
+    if (P->Wy > 32) P->Wy = 32;
+    P->Wz = pow2_floor(mz / grid);
+    if (P->Wz > 32) P->Wz = 32;
+    P->Wx = mxy / P->H;
+    if (P->Wx > 64) P->Wx = 64;
+    if (P->Wx < 1) P->Wx = 1;
+    {
+        const double sp = Sigma * sqrt(kPi);
+        const double d = sigma * sigma - Sigma * Sigma;
+        P->selfVF = 1.0 / (6.0 * kPi * P->eta * a) - 1.0 / (6.0 * kPi * P->eta * sp) +
+                    d / (12.0 * P->eta * sp * sp * sp) -
+                    d * d / (32.0 * P->eta * pow(Sigma, 5.0) * pow(kPi, 1.5));
+        const double sd = SigmaD * sqrt(kPi);
+        P->selfOT = 1.0 / (8.0 * kPi * P->eta * a * a * a) - 1.0 / (48.0 * P->eta * sd * sd * sd);
+    }
+
+    const size_t rs = real_size(P->precision);
+    const size_t M3 = (size_t)grid * grid * grid;
+    hipError_t e = hipSuccess;
+#define FCM_ALLOC(ptr, bytes)                                   \
+    do {                                                        \
+        if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes)); \
+    } while (0)
+    FCM_ALLOC(P->grid, 3 * M3 * rs);
+    FCM_ALLOC(P->twid, (size_t)grid * 2 * rs);
+    FCM_ALLOC(P->counts, (size_t)(P->nbins + P->ncells) * sizeof(int));
+    FCM_ALLOC(P->starts, (size_t)(P->nbins + 1 + P->ncells + 1) * sizeof(int));
+    FCM_ALLOC(P->keys, (size_t)2 * N * sizeof(int));
+    FCM_ALLOC(P->ranks, (size_t)2 * N * sizeof(int));
+    FCM_ALLOC(P->perm, (size_t)2 * N * sizeof(int));
+    FCM_ALLOC(P->scan_tmp, 2048 * sizeof(int));
+    FCM_ALLOC(P->grec, (size_t)N * grid_rec_size(P->precision));
+    FCM_ALLOC(P->prec, (size_t)N * sizeof(PairRec));
+    FCM_ALLOC(P->flag, 16 * sizeof(int));
+#undef FCM_ALLOC
+    if (e != hipSuccess) {
+        free_plan(P);
+        return map_err(e);
+    }
+    // twiddles exp(-2 pi i m / M) in extended precision, rounded once
+    {
+        const size_t n = (size_t)grid * 2;
+        void* host = malloc(n * rs);
+        if (!host) {
+            free_plan(P);
+            return FCM_ENOMEM;
+        }
+        for (int mm = 0; mm < grid; ++mm) {
+            const long double ang = -2.0L * 3.141592653589793238462643383279502884L * mm / grid;
+            const long double c = cosl(ang), s = sinl(ang);
+            if (P->precision == FCM_FP64) {
+                ((double*)host)[2 * mm] = (double)c;
+                ((double*)host)[2 * mm + 1] = (double)s;
+            } else {
+                ((float*)host)[2 * mm] = (float)c;
+                ((float*)host)[2 * mm + 1] = (float)s;
+            }
+        }
+        e = hipMemcpy(P->twid, host, n * rs, hipMemcpyHostToDevice);
+        free(host);
+        if (e == hipSuccess) e = hipMemset(P->flag, 0, 16 * sizeof(int));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            free_plan(P);
+            return map_err(e);
+        }
+    }
+    *out = P;
+    return FCM_OK;
+}
+
+int fcm_plan_destroy(fcm_plan_t p) {
+    if (!p) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    (void)hipDeviceSynchronize();
+    free_plan(p);
+    return FCM_OK;
+}
+
+int fcm_plan_info(fcm_plan_t p, int64_t* N, int* grid, int* support, int* precision,
+                  int* cells_per_axis) {
+    if (!p) return FCM_EINVAL;
+    if (N) *N = p->N;
+    if (grid) *grid = p->M;
+    if (support) *support = p->MG;
+    if (precision) *precision = p->precision;
+    if (cells_per_axis) *cells_per_axis = p->m;
+    return FCM_OK;
+}
+
+int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double* T, double* V,
+                 double* Omega, void* stream) {
+    if (!p || !pos || !F || !V) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    hipEvent_t* ev = call_events(p);
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    hipError_t e = sort_particles(p, pos, st);
+    if (e == hipSuccess) e = launch_gather_grid(p, pos, F, T, st);
+    mark(1);
+    if (e == hipSuccess) e = launch_spread(p, T != nullptr, p->grid, st);
+    if (e == hipSuccess) e = launch_solve(p, p->grid, st, ev ? ev + 2 : nullptr);
+    if (e == hipSuccess) e = launch_interp(p, p->grid, V, Omega, st);
+    mark(8);
+    if (e == hipSuccess && needs_correction(p)) {
+        e = launch_gather_pair(p, pos, F, T, st);
+        if (e == hipSuccess) e = launch_pair(p, V, Omega, T != nullptr, st);
+    }
+    mark(9);
+    return map_err(e);
+}
+
+int fcm_plan_set_timing(fcm_plan_t p, int enable) {
+    if (!p) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    if (enable && !p->events) {
+        const int n = kMaxTimedCalls * kEvPerCall;
+        p->events = (hipEvent_t*)calloc(n, sizeof(hipEvent_t));
+        if (!p->events) return FCM_ENOMEM;
+        p->ev_cap = kMaxTimedCalls;
+        for (int i = 0; i < n; ++i) {
+            hipError_t e = hipEventCreate(&p->events[i]);
+            if (e != hipSuccess) {
+                free_events(p);
+                return map_err(e);
+            }
+        }
+    }
+    p->timing = enable ? 1 : 0;
+    p->ev_calls = 0;
+    return FCM_OK;
+}
+
+int fcm_plan_stage_times(fcm_plan_t p, double* ms_out, int* ncalls) {
+    if (!p || !ms_out) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    for (int s = 0; s < FCM_NUM_STAGES; ++s) ms_out[s] = 0.0;
+    const int n = p->events ? p->ev_calls : 0;
+    if (n > 0) {
+        hipError_t e = hipEventSynchronize(p->events[(size_t)(n - 1) * kEvPerCall + kEvPerCall - 1]);
+        if (e != hipSuccess) return map_err(e);
+    }
+    for (int c = 0; c < n; ++c) {
+        hipEvent_t* ev = p->events + (size_t)c * kEvPerCall;
+        for (int s = 0; s < FCM_NUM_STAGES; ++s) {
+            float ms = 0.0f;
+            hipError_t e = hipEventElapsedTime(&ms, ev[s], ev[s + 1]);
+            if (e != hipSuccess) return map_err(e);
+            ms_out[s] += ms;
+        }
+    }
+    if (ncalls) *ncalls = n;
+    p->ev_calls = 0;
+    return FCM_OK;
+}
+
+int fcm_spread(fcm_plan_t p, const double* pos, const double* F, const double* T, void* grid_out,
+               void* stream) {
+    if (!p || !pos || !F || !grid_out) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    hipError_t e = sort_particles(p, pos, st);
+    if (e == hipSuccess) e = launch_gather_grid(p, pos, F, T, st);
+    if (e == hipSuccess) e = launch_spread(p, T != nullptr, grid_out, st);
+    return map_err(e);
+}
+
+int fcm_solve(fcm_plan_t p, void* grid_inout, void* stream) {
+    if (!p || !grid_inout) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    return map_err(launch_solve(p, grid_inout, st));
+}
+
+int fcm_interp(fcm_plan_t p, const double* pos, const void* grid_in, double* V, double* Omega,
+               void* stream) {
+    if (!p || !pos || !grid_in || !V) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    hipError_t e = sort_particles(p, pos, st);
+    if (e == hipSuccess) e = launch_gather_grid(p, pos, nullptr, nullptr, st);
+    if (e == hipSuccess) e = launch_interp(p, grid_in, V, Omega, st);
+    return map_err(e);
+}
+
+int fcm_correct(fcm_plan_t p, const double* pos, const double* F, const double* T, double* V,
+                double* Omega, void* stream) {
+    if (!p || !pos || !F || !V) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    if (!needs_correction(p)) return FCM_OK;
+    hipError_t e = sort_particles(p, pos, st);
+    if (e == hipSuccess) e = launch_gather_pair(p, pos, F, T, st);
+    if (e == hipSuccess) e = launch_pair(p, V, Omega, T != nullptr, st);
+    return map_err(e);
+}
+
+int fcm_plan_last_error(fcm_plan_t p) {
+    if (!p) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    hipError_t e = hipStreamSynchronize(p->last_stream);
+    if (e != hipSuccess) return map_err(e);
+    int h = 0;
+    e = hipMemcpy(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return map_err(e);
+    if (h) {
+        e = hipMemset(p->flag, 0, sizeof(int));
+        if (e != hipSuccess) return map_err(e);
+        return FCM_ENONFINITE;
+    }
+    return FCM_OK;
+}
+
+const char* fcm_status_string(int status) {
+    switch (status) {
+        case FCM_OK: return "ok";
+        case FCM_EINVAL: return "invalid argument";
+        case FCM_ENOMEM: return "out of memory";
+        case FCM_EDEVICE: return "HIP runtime error";
+        case FCM_ERANGE: return "cut-off radius must be below half the box";
+        case FCM_ENONFINITE: return "non-finite position in the last call";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,409 @@
+// The Fourier Stokes solve of fast FCM (Sec. 2.1 step 2, App. A):
+//   f -> f^ (3-D real-to-complex FFT) -> u^ = (I - k k^T/k^2) f^ / (eta k^2),
+//   u^(0) = 0, modes with index M/2 on any axis set to 0 -> u (complex-to-real).
+//
+// Five passes over the field, each a batch of 1-D transforms held in LDS:
+//   x : real-to-complex along x (half-length complex FFT + split), in place;
+//       the x-Nyquist coefficient is not stored (it is zeroed by the solve),
+//       so the spectrum (M/2 x M x M complex) has exactly the field's size;
+//   y : forward complex FFT along y;
+//   z : forward FFT along z, the projection, and the inverse FFT along z,
+//       all three components of a pencil at once (the fused middle pass);
+//   y : inverse complex FFT along y;
+//   x : complex-to-real along x.
+// Each 1-D transform is a mixed-radix (2, 3, 4, 8) Stockham autosort FFT:
+// stage s with radix R reads x[j + r n/R], twiddles by exp(+-2 pi i r k/(Ns R))
+// with k = j mod Ns, applies an R-point DFT and writes
+// y[(j div Ns) Ns R + k + r Ns].  Every thread holds its butterflies of a
+// stage in registers between a barrier-separated read and write, so a tile
+// is transformed in place.
+#include "fcm_internal.h"
+
+namespace fcm {
+
+namespace {
+
+constexpr int kFFTThreads = 256;
+
+template <typename R>
+__device__ inline C2<R> cadd(C2<R> a, C2<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ inline C2<R> csub(C2<R> a, C2<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ inline C2<R> cmul(C2<R> a, C2<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by DIR * i
+template <int DIR, typename R>
+__device__ inline C2<R> mul_i(C2<R> a) {
+    return DIR < 0 ? C2<R>{a.y, -a.x} : C2<R>{-a.y, a.x};
+}
+
+template <typename R, int RAD, int DIR>
+struct DFT;
+
+template <typename R, int DIR>
+struct DFT<R, 2, DIR> {
+    static __device__ inline void run(C2<R>* v) {
+        C2<R> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <typename R, int DIR>
+struct DFT<R, 3, DIR> {
+    static __device__ inline void run(C2<R>* v) {
+        const R h = (R)0.86602540378443864676;  // sqrt(3)/2
+        C2<R> a = v[0], s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        C2<R> m = {a.x - (R)0.5 * s.x, a.y - (R)0.5 * s.y};
+        C2<R> t = mul_i<DIR>(C2<R>{h * d.x, h * d.y});
+        v[0] = cadd(a, s);
+        v[1] = cadd(m, t);
+        v[2] = csub(m, t);
+    }
+};
+
+template <typename R, int DIR>
+struct DFT<R, 4, DIR> {
+    static __device__ inline void run(C2<R>* v) {
+        C2<R> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        C2<R> t2 = cadd(v[1], v[3]), t3 = mul_i<DIR>(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[2] = csub(t0, t2);
+        v[3] = csub(t1, t3);
+    }
+};
+
+template <typename R, int DIR>
+struct DFT<R, 8, DIR> {
+    static __device__ inline void run(C2<R>* v) {
+        C2<R> e[4] = {v[0], v[2], v[4], v[6]};
+        C2<R> o[4] = {v[1], v[3], v[5], v[7]};
+        DFT<R, 4, DIR>::run(e);
+        DFT<R, 4, DIR>::run(o);
+        const R c = (R)0.70710678118654752440;
+        // W8^k = exp(DIR 2 pi i k / 8)
+        C2<R> w1 = {c, DIR * c}, w3 = {-c, DIR * c};
+        C2<R> o1 = cmul(o[1], w1), o2 = mul_i<DIR>(o[2]), o3 = cmul(o[3], w3);
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    }
+};
+
+// One Stockham stage on an LDS tile of W lines of length n; element (w, idx)
+// lives at buf[w * sw + idx * sn].  tw[m] = exp(-2 pi i m / M), n divides M.
+template <typename R, int RAD, int DIR, int MAXB>
+__device__ void fft_stage(C2<R>* buf, const C2<R>* tw, int M, int n, int Ns, int W, int sw, int sn,
+                          bool wfast) {
+    const int nb = n / RAD;
+    const int total = nb * W;
+    const int tid = threadIdx.x;
+    const int tstep = M / (Ns * RAD);
+    C2<R> v[MAXB][RAD];
+    int jj[MAXB], ww[MAXB];
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int t = tid + q * kFFTThreads;
+        jj[q] = 0;
+        ww[q] = 0;
+        if (t < total) {
+            int w, j;
+            if (wfast) {
+                w = t % W;
+                j = t / W;
+            } else {
+                j = t % nb;
+                w = t / nb;
+            }
+            jj[q] = j;
+            ww[q] = w;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) v[q][r] = buf[w * sw + (j + r * nb) * sn];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int t = tid + q * kFFTThreads;
+        if (t < total) {
+            const int j = jj[q], w = ww[q];
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) {
+                C2<R> f = tw[r * k * tstep];
+                if (DIR > 0) f.y = -f.y;
+                v[q][r] = cmul(v[q][r], f);
+            }
+            DFT<R, RAD, DIR>::run(v[q]);
+            const int o = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) buf[w * sw + (o + r * Ns) * sn] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename R, int DIR, int MAXE>
+__device__ void fft_lines(C2<R>* buf, const C2<R>* tw, int M, const RadixPlan& rp, int W, int sw,
+                          int sn, bool wfast) {
+    int Ns = 1;
+    for (int s = 0; s < rp.nst; ++s) {
+        const int rad = rp.rad[s];
+        switch (rad) {
+            case 2: fft_stage<R, 2, DIR, (MAXE + 1) / 2>(buf, tw, M, rp.n, Ns, W, sw, sn, wfast); break;
+            case 3: fft_stage<R, 3, DIR, (MAXE + 2) / 3>(buf, tw, M, rp.n, Ns, W, sw, sn, wfast); break;
+            case 4: fft_stage<R, 4, DIR, (MAXE + 3) / 4>(buf, tw, M, rp.n, Ns, W, sw, sn, wfast); break;
+            default: fft_stage<R, 8, DIR, (MAXE + 7) / 8>(buf, tw, M, rp.n, Ns, W, sw, sn, wfast); break;
+        }
+        Ns *= rad;
+    }
+}
+
+template <typename R>
+__device__ inline void load_twiddles(C2<R>* tw, const C2<R>* __restrict__ twg, int M) {
+    for (int e = threadIdx.x; e < M; e += kFFTThreads) tw[e] = twg[e];
+}
+
+// x pass, forward: Wx real lines of length M per block -> M/2 complex each
+template <typename R, int MAXE>
+__global__ __launch_bounds__(kFFTThreads) void k_fft_x_r2c(R* __restrict__ grid,
+                                                           const C2<R>* __restrict__ twg, int M,
+                                                           RadixPlan rpH, int Wx, int nlines) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
+    C2<R>* buf = tw + M;
+    const int H = M / 2, sw = H + 1;
+    const int line0 = blockIdx.x * Wx;
+    C2<R>* g = reinterpret_cast<C2<R>*>(grid);
+    load_twiddles(tw, twg, M);
+    for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
+        const int w = e / H, m = e % H, l = line0 + w;
+        buf[w * sw + m] = (l < nlines) ? g[(size_t)l * H + m] : C2<R>{0, 0};
+    }
+    __syncthreads();
+    fft_lines<R, -1, MAXE>(buf, tw, M, rpH, Wx, sw, 1, false);
+    for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
+        const int w = e / H, k = e % H, l = line0 + w;
+        if (l >= nlines) continue;
+        const C2<R> Z = buf[w * sw + k];
+        C2<R> Zc = buf[w * sw + (k == 0 ? 0 : H - k)];
+        Zc.y = -Zc.y;
+        const C2<R> S = cadd(Z, Zc), D = csub(Z, Zc);
+        const C2<R> WD = cmul(tw[k], D);  // exp(-2 pi i k/M) (Z_k - conj Z_{H-k})
+        g[(size_t)l * H + k] = C2<R>{(R)0.5 * (S.x + WD.y), (R)0.5 * (S.y - WD.x)};
+    }
+}
+
+// x pass, inverse: M/2 complex (x-Nyquist taken as 0) -> M reals, unnormalised
+template <typename R, int MAXE>
+__global__ __launch_bounds__(kFFTThreads) void k_fft_x_c2r(R* __restrict__ grid,
+                                                           const C2<R>* __restrict__ twg, int M,
+                                                           RadixPlan rpH, int Wx, int nlines) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
+    C2<R>* buf = tw + M;
+    const int H = M / 2, sw = H + 1;
+    const int line0 = blockIdx.x * Wx;
+    C2<R>* g = reinterpret_cast<C2<R>*>(grid);
+    load_twiddles(tw, twg, M);
+    for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
+        const int w = e / H, m = e % H, l = line0 + w;
+        buf[w * sw + m] = (l < nlines) ? g[(size_t)l * H + m] : C2<R>{0, 0};
+    }
+    __syncthreads();
+    C2<R> zr[MAXE];
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+        const int e = threadIdx.x + q * kFFTThreads;
+        if (e < Wx * H) {
+            const int w = e / H, k = e % H;
+            const C2<R> X = buf[w * sw + k];
+            C2<R> Xc = {0, 0};
+            if (k > 0) {
+                Xc = buf[w * sw + H - k];
+                Xc.y = -Xc.y;
+            }
+            const C2<R> E = cadd(X, Xc);
+            C2<R> wk = tw[k];
+            wk.y = -wk.y;  // exp(+2 pi i k / M)
+            const C2<R> O = cmul(csub(X, Xc), wk);
+            zr[q] = C2<R>{E.x - O.y, E.y + O.x};
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+        const int e = threadIdx.x + q * kFFTThreads;
+        if (e < Wx * H) buf[(e / H) * sw + e % H] = zr[q];
+    }
+    __syncthreads();
+    fft_lines<R, 1, MAXE>(buf, tw, M, rpH, Wx, sw, 1, false);
+    for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
+        const int w = e / H, m = e % H, l = line0 + w;
+        if (l < nlines) g[(size_t)l * H + m] = buf[w * sw + m];
+    }
+}
+
+// y pass: batches of W consecutive kx columns of one (component, z) plane
+template <typename R, int DIR, int MAXE>
+__global__ __launch_bounds__(kFFTThreads) void k_fft_y(C2<R>* __restrict__ spec,
+                                                       const C2<R>* __restrict__ twg, int M,
+                                                       RadixPlan rpM, int W) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
+    C2<R>* buf = tw + M;
+    const int H = M / 2;
+    const int ng = (H + W - 1) / W;
+    const int g = blockIdx.x % ng;
+    const int rest = blockIdx.x / ng;  // c * M + z
+    const int kx0 = g * W;
+    const int Wv = min(W, H - kx0);
+    C2<R>* base = spec + (size_t)rest * M * H + kx0;
+    load_twiddles(tw, twg, M);
+    for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
+        const int w = e % W, y = e / W;
+        buf[e] = (w < Wv) ? base[(size_t)y * H + w] : C2<R>{0, 0};
+    }
+    __syncthreads();
+    fft_lines<R, DIR, MAXE>(buf, tw, M, rpM, W, 1, W, true);
+    for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
+        const int w = e % W, y = e / W;
+        if (w < Wv) base[(size_t)y * H + w] = buf[e];
+    }
+}
+
+struct ProjArgs {
+    double kunit;   // 2 pi / L
+    double scale;   // 1 / (eta M^3)
+};
+
+// z pass: forward FFT along z, projection / (eta k^2), inverse FFT along z
+template <typename R, int MAXE>
+__global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__ spec,
+                                                             const C2<R>* __restrict__ twg, int M,
+                                                             RadixPlan rpM, int W, ProjArgs pa) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
+    C2<R>* buf = tw + M;  // 3 components, each M x W
+    const int H = M / 2;
+    const int ng = (H + W - 1) / W;
+    const int g = blockIdx.x % ng;
+    const int y = blockIdx.x / ng;
+    const int kx0 = g * W;
+    const int Wv = min(W, H - kx0);
+    const size_t cstride = (size_t)M * M * H;
+    const size_t zstride = (size_t)M * H;
+    C2<R>* base = spec + (size_t)y * H + kx0;
+    load_twiddles(tw, twg, M);
+    for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
+        const int w = e % W, z = e / W;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            buf[c * M * W + e] = (w < Wv) ? base[c * cstride + (size_t)z * zstride + w] : C2<R>{0, 0};
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) fft_lines<R, -1, MAXE>(buf + c * M * W, tw, M, rpM, W, 1, W, true);
+    const R ku = (R)pa.kunit;
+    const R sc = (R)pa.scale;
+    const int jy = y < H ? y : y - M;
+    for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
+        const int w = e % W, z = e / W;
+        const int jx = kx0 + w;
+        const int jz = z < H ? z : z - M;
+        const bool zero = (w >= Wv) || (y == H) || (z == H) || (jx == 0 && jy == 0 && jz == 0);
+        C2<R> f0 = buf[e], f1 = buf[M * W + e], f2 = buf[2 * M * W + e];
+        C2<R> u0 = {0, 0}, u1 = {0, 0}, u2 = {0, 0};
+        if (!zero) {
+            const R kx = ku * (R)jx, ky = ku * (R)jy, kz = ku * (R)jz;
+            const R k2 = kx * kx + ky * ky + kz * kz;
+            const R ik2 = (R)1 / k2;
+            const C2<R> kf = {(kx * f0.x + ky * f1.x + kz * f2.x) * ik2,
+                              (kx * f0.y + ky * f1.y + kz * f2.y) * ik2};
+            const R s = sc * ik2;
+            u0 = C2<R>{(f0.x - kx * kf.x) * s, (f0.y - kx * kf.y) * s};
+            u1 = C2<R>{(f1.x - ky * kf.x) * s, (f1.y - ky * kf.y) * s};
+            u2 = C2<R>{(f2.x - kz * kf.x) * s, (f2.y - kz * kf.y) * s};
+        }
+        buf[e] = u0;
+        buf[M * W + e] = u1;
+        buf[2 * M * W + e] = u2;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) fft_lines<R, 1, MAXE>(buf + c * M * W, tw, M, rpM, W, 1, W, true);
+    for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
+        const int w = e % W, z = e / W;
+        if (w < Wv) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) base[c * cstride + (size_t)z * zstride + w] = buf[c * M * W + e];
+        }
+    }
+}
+
+template <typename R, int MX, int MZ>
+hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* ev) {
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    const int M = P->M, H = P->H;
+    const C2<R>* tw = (const C2<R>*)P->twid;
+    C2<R>* spec = (C2<R>*)grid;
+    const int nlines = 3 * M * M;
+    const size_t cs = sizeof(C2<R>);
+    ProjArgs pa;
+    pa.kunit = 2.0 * 3.14159265358979323846 / P->L;
+    pa.scale = 1.0 / (P->eta * (double)M * M * M);
+    mark(0);
+    {
+        const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;
+        hipLaunchKernelGGL((k_fft_x_r2c<R, MX>), dim3((nlines + P->Wx - 1) / P->Wx),
+                           dim3(kFFTThreads), shm, st, grid, tw, M, P->radH, P->Wx, nlines);
+    }
+    mark(1);
+    const int ngy = (H + P->Wy - 1) / P->Wy;
+    const size_t shy = (M + (size_t)P->Wy * M) * cs;
+    hipLaunchKernelGGL((k_fft_y<R, -1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec,
+                       tw, M, P->radM, P->Wy);
+    mark(2);
+    {
+        const int ngz = (H + P->Wz - 1) / P->Wz;
+        const size_t shz = (M + 3 * (size_t)P->Wz * M) * cs;
+        hipLaunchKernelGGL((k_fft_z_solve<R, MZ>), dim3(ngz * M), dim3(kFFTThreads), shz, st, spec,
+                           tw, M, P->radM, P->Wz, pa);
+    }
+    mark(3);
+    hipLaunchKernelGGL((k_fft_y<R, 1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec, tw,
+                       M, P->radM, P->Wy);
+    mark(4);
+    {
+        const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;
+        hipLaunchKernelGGL((k_fft_x_c2r<R, MX>), dim3((nlines + P->Wx - 1) / P->Wx),
+                           dim3(kFFTThreads), shm, st, grid, tw, M, P->radH, P->Wx, nlines);
+    }
+    mark(5);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// elements per thread of the x/y passes and of the z pass
+int fft_maxe(int precision, bool zpass) {
+    if (precision == FCM_FP64) return zpass ? 4 : 8;
+    return zpass ? 8 : 16;
+}
+
+hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st, hipEvent_t* ev) {
+    if (P->precision == FCM_FP64) return solve_r<double, 8, 4>(P, (double*)grid, st, ev);
+    return solve_r<float, 16, 8>(P, (float*)grid, st, ev);
+}
+
+}  // namespace fcm

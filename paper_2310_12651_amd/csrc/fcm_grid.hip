@@ -1,0 +1,403 @@
+// Grid operators of fast FCM: spreading J~^dagger[F] + N~^dagger[T] and
+// interpolation J~[u], N~[u] (Sec. 2.1, Sec. 3.1, Sec. 3.4).
+//
+// Spreading is done in gather form: one 64-lane wavefront owns a tile of
+// TX x TY grid columns and TZ points along z, scans the particles of the grid
+// bins whose supports can reach the tile (particles are sorted by the bin of
+// their first support point), stages the contributing ones in LDS, and
+// accumulates their kernel values in registers.  Every grid point is written
+// exactly once, with one coalesced store per point: no global atomics.
+//
+// The modified force kernel is Delta~(d) = Delta(d; Sigma) (A + B |d|^2) with
+// A = 1 - 3c/Sigma^2, B = c/Sigma^4, c = (sigma^2 - Sigma^2)/2 (the operator
+// (1 + c lap) applied to the Gaussian), and the torque kernel is
+// (1/2 Sigma_D^2) Delta(d; Sigma_D) (T x d) (Sec. 3.4).  Both are separable
+// Gaussians times low-order polynomials, so along z the sum is factorised:
+// each lane forms its (x, y) column factors once per particle and then needs
+// only a few FMAs per z point.
+//
+// Interpolation is particle-major: one wavefront per particle, lanes over the
+// (x, y) columns of the M_G^3 support, a factorised sum along z per lane, and
+// a butterfly shuffle reduction across the wavefront.
+#include "fcm_internal.h"
+
+namespace fcm {
+
+namespace {
+
+constexpr int kChunk = 64;
+
+template <typename R>
+struct alignas(16) ZTab {
+    R g;    // Gaussian of width Sigma (unnormalised)
+    R d;    // displacement
+    R d2;   // displacement squared
+    R gD;   // Gaussian of width Sigma_D
+};
+
+__device__ inline float fexp2(float x) { return exp2f(x); }
+__device__ inline double fexp2(double x) { return exp2(x); }
+
+template <bool K, typename R>
+__device__ inline void kadd(R& s, R& c, R v) {
+    if (K) {
+        R y = v - c;
+        R t = s + y;
+        c = (t - s) - y;
+        s = t;
+    } else {
+        s += v;
+    }
+}
+
+template <typename R, int TZ, bool KAHAN, bool TORQUE>
+__global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ rec,
+                                               const int* __restrict__ bin_start,
+                                               R* __restrict__ grid, GridArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    GridRec<R>* stg = reinterpret_cast<GridRec<R>*>(smem);
+    ZTab<R>* zt = reinterpret_cast<ZTab<R>*>(smem + kChunk * sizeof(GridRec<R>));
+
+    const int lane = threadIdx.x;
+    int tile = blockIdx.x;
+    if (a.remap8) {
+        // consecutive workgroups go to different XCDs; give each XCD a
+        // contiguous run of tiles so neighbouring tiles share its L2
+        const int per = gridDim.x >> 3;
+        tile = (tile & 7) * per + (tile >> 3);
+    }
+    const int M = a.M, MG = a.MG;
+    const int btx = tile % a.nbx;
+    const int rem = tile / a.nbx;
+    const int bty = rem % a.nby;
+    const int btz = rem / a.nby;
+    const int X0 = btx * a.TX, Y0 = bty * a.TY, Z0 = btz * TZ;
+    const int li = lane % a.TX, lj = lane / a.TX;
+    const bool lact = lj < a.TY;
+    const int gxp = X0 + li, gyp = Y0 + (lact ? lj : 0);
+    const R dx = a.dx;
+
+    R acc[3][TZ], cmp[3][TZ];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) {
+            acc[c][k] = 0;
+            cmp[c][k] = 0;
+        }
+
+    for (int oz = 0; oz <= a.backz; ++oz) {
+        int bz = btz - oz;
+        if (bz < 0) bz += a.nbz;
+        for (int oy = 0; oy <= a.backy; ++oy) {
+            int by = bty - oy;
+            if (by < 0) by += a.nby;
+            for (int ox = 0; ox <= a.backx; ++ox) {
+                int bx = btx - ox;
+                if (bx < 0) bx += a.nbx;
+                const int b = bx + a.nbx * (by + a.nby * bz);
+                const int beg = bin_start[b], end = bin_start[b + 1];
+                for (int base = beg; base < end; base += kChunk) {
+                    const int p = base + lane;
+                    bool take = false;
+                    GridRec<R> r;
+                    if (p < end) {
+                        r = rec[p];
+                        int d0x = X0 - r.s[0];
+                        if (d0x < 0) d0x += M;
+                        int d0y = Y0 - r.s[1];
+                        if (d0y < 0) d0y += M;
+                        int d0z = Z0 - r.s[2];
+                        if (d0z < 0) d0z += M;
+                        take = (d0x < MG || d0x > M - a.TX) && (d0y < MG || d0y > M - a.TY) &&
+                               (d0z < MG || d0z > M - TZ);
+                    }
+                    const unsigned long long mask = __ballot(take);
+                    const int cnt = __popcll(mask);
+                    if (take) {
+                        const int slot = __popcll(mask & ((1ull << lane) - 1ull));
+                        stg[slot] = r;
+                        for (int t = 0; t < MG; ++t) {
+                            const R d = ((R)t - r.f[2]) * dx;
+                            const R d2 = d * d;
+                            ZTab<R> e;
+                            e.g = fexp2(-d2 * a.e2);
+                            e.d = d;
+                            e.d2 = d2;
+                            e.gD = a.same_width ? e.g : fexp2(-d2 * a.e2D);
+                            zt[slot * MG + t] = e;
+                        }
+                    }
+                    __syncthreads();
+                    for (int q = 0; q < cnt; ++q) {
+                        const int sx = __builtin_amdgcn_readfirstlane(stg[q].s[0]);
+                        const int sy = __builtin_amdgcn_readfirstlane(stg[q].s[1]);
+                        const int sz = __builtin_amdgcn_readfirstlane(stg[q].s[2]);
+                        int dxi = gxp - sx;
+                        if (dxi < 0) dxi += M;
+                        int dyi = gyp - sy;
+                        if (dyi < 0) dyi += M;
+                        const bool in = lact && dxi < MG && dyi < MG;
+                        const R dxv = ((R)dxi - stg[q].f[0]) * dx;
+                        const R dyv = ((R)dyi - stg[q].f[1]) * dx;
+                        const R x2 = dxv * dxv, y2 = dyv * dyv;
+                        const R wx = in ? fexp2(-x2 * a.e2) : (R)0;
+                        const R wy = fexp2(-y2 * a.e2);
+                        const R gxy = wx * wy;
+                        const R base_w = gxy * (a.A + a.B * (x2 + y2));
+                        const R gB = gxy * a.B;
+                        const R F0 = stg[q].F[0], F1 = stg[q].F[1], F2 = stg[q].F[2];
+                        R gxyD = gxy, T0 = 0, T1 = 0, ax = 0, ay = 0, az = 0;
+                        if (TORQUE) {
+                            if (!a.same_width)
+                                gxyD = in ? fexp2(-x2 * a.e2D) * fexp2(-y2 * a.e2D) : (R)0;
+                            T0 = stg[q].T[0];
+                            T1 = stg[q].T[1];
+                            const R T2 = stg[q].T[2];
+                            ax = -T2 * dyv;
+                            ay = T2 * dxv;
+                            az = T0 * dyv - T1 * dxv;
+                        }
+                        int dz0 = Z0 - sz;
+                        if (dz0 < 0) dz0 += M;
+                        const ZTab<R>* zq = zt + q * MG;
+#pragma unroll
+                        for (int k = 0; k < TZ; ++k) {
+                            int dzi = dz0 + k;
+                            if (dzi >= M) dzi -= M;
+                            if (dzi < MG) {
+                                const ZTab<R> e = zq[dzi];
+                                const R w = e.g * (base_w + gB * e.d2);
+                                if (TORQUE) {
+                                    const R wt = e.gD * gxyD;
+                                    const R tx = ax + T1 * e.d;
+                                    const R ty = ay - T0 * e.d;
+                                    kadd<KAHAN>(acc[0][k], cmp[0][k], w * F0 + wt * tx);
+                                    kadd<KAHAN>(acc[1][k], cmp[1][k], w * F1 + wt * ty);
+                                    kadd<KAHAN>(acc[2][k], cmp[2][k], w * F2 + wt * az);
+                                } else {
+                                    kadd<KAHAN>(acc[0][k], cmp[0][k], w * F0);
+                                    kadd<KAHAN>(acc[1][k], cmp[1][k], w * F1);
+                                    kadd<KAHAN>(acc[2][k], cmp[2][k], w * F2);
+                                }
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+    }
+    if (lact) {
+        const size_t M3 = (size_t)M * M * M;
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) {
+            const size_t idx = ((size_t)(Z0 + k) * M + gyp) * M + gxp;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) grid[c * M3 + idx] = KAHAN ? acc[c][k] - cmp[c][k] : acc[c][k];
+        }
+    }
+}
+
+template <typename R>
+__device__ inline R wave_sum(R v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename R, bool OMEGA, bool SAMEW>
+__global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ rec,
+                                                const R* __restrict__ grid, double* __restrict__ V,
+                                                double* __restrict__ W, GridArgs<R> a,
+                                                double scaleV, double scaleW) {
+    __shared__ ZTab<R> zt[4][kMaxSupport];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + wave;
+    const bool live = p < a.N;
+    const GridRec<R> r = rec[live ? p : a.N - 1];
+    const int M = a.M, MG = a.MG;
+    const R dx = a.dx;
+    if (lane < MG) {
+        const R d = ((R)lane - r.f[2]) * dx;
+        ZTab<R> e;
+        e.d = d;
+        e.d2 = d * d;
+        e.g = fexp2(-e.d2 * a.e2);
+        e.gD = SAMEW ? e.g : fexp2(-e.d2 * a.e2D);
+        zt[wave][lane] = e;
+    }
+    __syncthreads();
+    const size_t M3 = (size_t)M * M * M;
+    R v0 = 0, v1 = 0, v2 = 0, o0 = 0, o1 = 0, o2 = 0;
+    const int ncol = MG * MG;
+    for (int q0 = 0; q0 < ncol; q0 += 64) {
+        const int q = q0 + lane;
+        const bool ok = q < ncol;
+        const int i = ok ? q % MG : 0;
+        const int j = ok ? q / MG : 0;
+        int x = r.s[0] + i;
+        if (x >= M) x -= M;
+        int y = r.s[1] + j;
+        if (y >= M) y -= M;
+        const R dxv = ((R)i - r.f[0]) * dx;
+        const R dyv = ((R)j - r.f[1]) * dx;
+        const R x2 = dxv * dxv, y2 = dyv * dyv;
+        const R gxy = ok ? fexp2(-x2 * a.e2) * fexp2(-y2 * a.e2) : (R)0;
+        R A0[3] = {0, 0, 0}, A2[3] = {0, 0, 0}, D1[3] = {0, 0, 0}, D0[3] = {0, 0, 0};
+        const R* colp = grid + (size_t)y * M + x;
+        for (int k = 0; k < MG; ++k) {
+            int z = r.s[2] + k;
+            if (z >= M) z -= M;
+            const ZTab<R> e = zt[wave][k];
+            const size_t off = (size_t)z * M * M;
+            const R u0 = colp[off], u1 = colp[M3 + off], u2 = colp[2 * M3 + off];
+            A0[0] += e.g * u0;
+            A0[1] += e.g * u1;
+            A0[2] += e.g * u2;
+            const R gd2 = e.g * e.d2;
+            A2[0] += gd2 * u0;
+            A2[1] += gd2 * u1;
+            A2[2] += gd2 * u2;
+            if (OMEGA) {
+                const R gdd = e.gD * e.d;
+                D1[0] += gdd * u0;
+                D1[1] += gdd * u1;
+                D1[2] += gdd * u2;
+                if (!SAMEW) {
+                    D0[0] += e.gD * u0;
+                    D0[1] += e.gD * u1;
+                    D0[2] += e.gD * u2;
+                }
+            }
+        }
+        const R cw = gxy * (a.A + a.B * (x2 + y2));
+        const R cb = gxy * a.B;
+        v0 += cw * A0[0] + cb * A2[0];
+        v1 += cw * A0[1] + cb * A2[1];
+        v2 += cw * A0[2] + cb * A2[2];
+        if (OMEGA) {
+            R gD = gxy;
+            const R* S0 = A0;
+            if (!SAMEW) {
+                gD = ok ? fexp2(-x2 * a.e2D) * fexp2(-y2 * a.e2D) : (R)0;
+                S0 = D0;
+            }
+            // (d x u): x: dy u_z - dz u_y ; y: dz u_x - dx u_z ; z: dx u_y - dy u_x
+            o0 += gD * (dyv * S0[2] - D1[1]);
+            o1 += gD * (D1[0] - dxv * S0[2]);
+            o2 += gD * (dxv * S0[1] - dyv * S0[0]);
+        }
+    }
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    v2 = wave_sum(v2);
+    if (OMEGA) {
+        o0 = wave_sum(o0);
+        o1 = wave_sum(o1);
+        o2 = wave_sum(o2);
+    }
+    if (live && lane == 0) {
+        const int64_t n = r.orig;
+        V[3 * n + 0] = (double)v0 * scaleV;
+        V[3 * n + 1] = (double)v1 * scaleV;
+        V[3 * n + 2] = (double)v2 * scaleV;
+        if (OMEGA) {
+            W[3 * n + 0] = (double)o0 * scaleW;
+            W[3 * n + 1] = (double)o1 * scaleW;
+            W[3 * n + 2] = (double)o2 * scaleW;
+        }
+    }
+}
+
+template <typename R>
+GridArgs<R> make_args(const fcm_plan_impl* P) {
+    GridArgs<R> a;
+    a.M = P->M;
+    a.MG = P->MG;
+    a.N = (int)P->N;
+    a.TX = P->TX;
+    a.TY = P->TY;
+    a.TZ = P->TZ;
+    a.nbx = P->nbx;
+    a.nby = P->nby;
+    a.nbz = P->nbz;
+    a.backx = P->backx;
+    a.backy = P->backy;
+    a.backz = P->backz;
+    a.remap8 = (P->nbins % 8 == 0) ? 1 : 0;
+    a.dx = (R)P->dx;
+    const double log2e = 1.4426950408889634074;
+    a.e2 = (R)(log2e / (2.0 * P->Sigma * P->Sigma));
+    a.e2D = (R)(log2e / (2.0 * P->SigmaD * P->SigmaD));
+    const double c = 0.5 * (P->sigma * P->sigma - P->Sigma * P->Sigma);
+    const double S2 = P->Sigma * P->Sigma;
+    a.A = (R)(1.0 - 3.0 * c / S2);
+    a.B = (R)(c / (S2 * S2));
+    a.dV = (R)(P->dx * P->dx * P->dx);
+    a.same_width = (P->SigmaD == P->Sigma) ? 1 : 0;
+    return a;
+}
+
+template <typename R, int TZ, bool K>
+hipError_t spread_tz(const fcm_plan_impl* P, bool torque, R* grid, hipStream_t st) {
+    GridArgs<R> a = make_args<R>(P);
+    const size_t shm = kChunk * (sizeof(GridRec<R>) + (size_t)P->MG * sizeof(ZTab<R>));
+    dim3 g(P->nbins), b(64);
+    if (torque)
+        hipLaunchKernelGGL((k_spread<R, TZ, K, true>), g, b, shm, st,
+                           (const GridRec<R>*)P->grec, P->starts, grid, a);
+    else
+        hipLaunchKernelGGL((k_spread<R, TZ, K, false>), g, b, shm, st,
+                           (const GridRec<R>*)P->grec, P->starts, grid, a);
+    return hipGetLastError();
+}
+
+template <typename R, bool K>
+hipError_t spread_r(const fcm_plan_impl* P, bool torque, R* grid, hipStream_t st) {
+    switch (P->TZ) {
+        case 16: return spread_tz<R, 16, K>(P, torque, grid, st);
+        case 12: return spread_tz<R, 12, K>(P, torque, grid, st);
+        case 8: return spread_tz<R, 8, K>(P, torque, grid, st);
+        case 6: return spread_tz<R, 6, K>(P, torque, grid, st);
+        case 4: return spread_tz<R, 4, K>(P, torque, grid, st);
+        case 2: return spread_tz<R, 2, K>(P, torque, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W, hipStream_t st) {
+    GridArgs<R> a = make_args<R>(P);
+    const double pi = 3.14159265358979323846;
+    const double dV = P->dx * P->dx * P->dx;
+    const double scaleV = dV * pow(2.0 * pi * P->Sigma * P->Sigma, -1.5);
+    const double scaleW =
+        dV * pow(2.0 * pi * P->SigmaD * P->SigmaD, -1.5) / (2.0 * P->SigmaD * P->SigmaD);
+    dim3 g((unsigned)((P->N + 3) / 4)), b(256);
+    const GridRec<R>* rec = (const GridRec<R>*)P->grec;
+    if (W == nullptr)
+        hipLaunchKernelGGL((k_interp<R, false, true>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+    else if (a.same_width)
+        hipLaunchKernelGGL((k_interp<R, true, true>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+    else
+        hipLaunchKernelGGL((k_interp<R, true, false>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st) {
+    if (P->precision == FCM_FP64) return spread_r<double, false>(P, torque, (double*)grid, st);
+    if (P->kahan) return spread_r<float, true>(P, torque, (float*)grid, st);
+    return spread_r<float, false>(P, torque, (float*)grid, st);
+}
+
+hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, double* W,
+                         hipStream_t st) {
+    if (P->precision == FCM_FP64) return interp_r<double>(P, (const double*)grid, V, W, st);
+    return interp_r<float>(P, (const float*)grid, V, W, st);
+}
+
+}  // namespace fcm

@@ -1,0 +1,142 @@
+// Internal definitions shared by the translation units of the fast-FCM HIP
+// library (plan layout, per-particle records, kernel argument blocks and
+// launchers).  Not part of the public C ABI (include/fcm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fcm.h"
+
+namespace fcm {
+
+constexpr int kMaxRadixStages = 16;
+constexpr int kMaxSupport = 32;      // largest M_G accepted
+constexpr int kMaxGrid = 1024;       // largest grid per axis accepted
+constexpr int kMaxCellsPerAxis = 128;
+
+template <typename R>
+struct C2 {
+    R x, y;
+};
+
+// Per-particle record of the grid kernels, in grid-bin order.  s[] is the
+// first support point along each axis (mod M), f[] the particle coordinate in
+// grid units minus the unwrapped first support point (so the displacement of
+// support point j is (j - f) dx), F and T are the force and the torque scaled
+// by the kernel normalisation (and by 1/(2 Sigma_D^2) for T).
+template <typename R>
+struct alignas(16) GridRec {
+    int s[3];
+    int orig;
+    R f[3];
+    R F[3];
+    R T[3];
+};
+
+// Per-particle record of the pair kernel, in pair-cell order.
+struct alignas(16) PairRec {
+    double y[3];
+    int orig;
+    int cell;
+    double F[3];
+    double T[3];
+};
+
+struct RadixPlan {
+    int n;                         // transform length
+    int nst;                       // number of stages
+    int rad[kMaxRadixStages];      // radices in application order
+};
+
+// Scalars of the grid kernels (one plan).
+template <typename R>
+struct GridArgs {
+    int M, MG, N;
+    int TX, TY, TZ;                // spread tile (points)
+    int nbx, nby, nbz;             // tiles (= bins) per axis
+    int backx, backy, backz;       // bins scanned before the tile's own
+    int remap8;                    // 1 = spread XCD-aware tile remap
+    R dx;                          // grid spacing
+    R e2;                          // log2(e) / (2 Sigma^2)
+    R e2D;                         // log2(e) / (2 Sigma_D^2)
+    R A, B;                        // Delta~ = Delta (A + B r^2)
+    R dV;                          // dx^3
+    int same_width;                // Sigma_D == Sigma
+};
+
+struct PairArgs {
+    int N, m;                      // particles, cells per axis
+    double L, cw, rc2;
+    double eta, sigma, sigmaD, Sigma, SigmaD;
+    double selfVF, selfOT;
+    int with_pairs;                // 0 = only self corrections (R_c = 0)
+};
+
+}  // namespace fcm
+
+struct fcm_plan_impl {
+    int device;
+    int64_t N;
+    double L, a, eta;
+    double sigma, sigmaD, Sigma, SigmaD;
+    double rc, dx;
+    int M, H, MG;
+    int precision, kahan;
+    // spread tiling / grid bins
+    int TX, TY, TZ, nbx, nby, nbz, nbins;
+    int backx, backy, backz;
+    // pair cells
+    int m, ncells;
+    // FFT
+    fcm::RadixPlan radM, radH;
+    int Wx, Wy, Wz;
+    // closed-form constants
+    double selfVF, selfOT;
+    // device buffers
+    void* grid;            // 3 M^3 reals (working field / spectrum)
+    void* twid;            // M complex: exp(-2 pi i m / M), in the grid precision
+    int* counts;           // nbins + ncells (+2) counters
+    int* starts;           // exclusive scans: bins then cells
+    int* keys;             // 2N keys (bin, cell)
+    int* ranks;            // 2N ranks within key
+    int* perm;             // 2N: grid order then pair order
+    int* scan_tmp;         // block sums of the scan
+    void* grec;            // N GridRec
+    fcm::PairRec* prec;    // N PairRec
+    int* flag;             // [0] = non-finite position seen
+    hipStream_t last_stream;
+    int sorted_valid;
+    // per-stage timing
+    int timing;
+    int ev_calls;           // calls recorded
+    int ev_cap;             // event sets allocated
+    hipEvent_t* events;     // ev_cap * (FCM_NUM_STAGES + 1)
+};
+
+// ---- launchers (each enqueues on `st`; return hipError_t of the launch) ----
+namespace fcm {
+
+hipError_t launch_fill(int* p, int n, int v, hipStream_t st);
+// wrap + hash (Sec. 4, spatial hashing) for the grid bins and the pair cells
+hipError_t launch_hash(const fcm_plan_impl* P, const double* pos, hipStream_t st);
+// exclusive scan of counts[0..n) into starts[0..n], starts[n] = total
+hipError_t launch_scan(const int* counts, int* starts, int n, int* tmp, hipStream_t st);
+// counting-sort scatter and in-segment ordering by original index
+hipError_t launch_scatter(const fcm_plan_impl* P, hipStream_t st);
+// gather the sorted per-particle records
+hipError_t launch_gather_grid(const fcm_plan_impl* P, const double* pos, const double* F,
+                              const double* T, hipStream_t st);
+hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const double* F,
+                              const double* T, hipStream_t st);
+
+hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st);
+hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, double* W,
+                         hipStream_t st);
+// ev: NULL or 6 events recorded before/between/after the five FFT passes
+hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st,
+                        hipEvent_t* ev = nullptr);
+hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool torque,
+                       hipStream_t st);
+
+}  // namespace fcm

@@ -1,0 +1,299 @@
+// Particle bookkeeping of fast FCM (Sec. 4, spatial hashing and sorting):
+// periodic wrap, hashing into grid bins (for the spreading tiles) and into
+// pair cells of width >= R_c (m = max(int(L/R_c), 3) per axis), a counting
+// sort by key, and the gather of the sorted per-particle records.
+//
+// The counting sort places particles with atomics and then orders every
+// segment by original index, so the sorted order is (key, original index):
+// deterministic from run to run.
+#include "fcm_internal.h"
+
+namespace fcm {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPerThread = 16;
+constexpr int kScanTile = kScanThreads * kScanPerThread;   // 4096
+constexpr int kScanTopThreads = 1024;
+
+struct HashArgs {
+    int N, M, MG;
+    int TX, TY, TZ, nbx, nby, nbz, nbins;
+    int m;
+    double L, dx, cw;
+};
+
+// wrap into [0, L); non-finite values, and values too large for the wrap to
+// land in [0, L), become 0 and raise the plan's flag.  Every index derived
+// from the result is therefore in range.
+__device__ inline double wrap_coord(double y, double L, int* bad) {
+    if (!isfinite(y)) {
+        *bad = 1;
+        return 0.0;
+    }
+    double w = y - L * floor(y / L);
+    if (w >= L) w -= L;
+    if (w < 0.0) w = 0.0;     // rounding just below 0
+    if (!(w < L)) {
+        *bad = 1;
+        w = 0.0;
+    }
+    return w;
+}
+
+// first support point (unwrapped) of a coordinate w in [0, L): floor(w/dx - M_G/2) + 1
+__device__ inline int support_start(double w, double dx, int MG) {
+    return (int)floor(w / dx - 0.5 * MG) + 1;
+}
+
+__device__ inline int wrap_index(int s, int M) {
+    if (s < 0) s += M;
+    if (s >= M) s -= M;
+    return s;
+}
+
+__global__ void k_fill(int* __restrict__ p, int n, int v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_hash(const double* __restrict__ pos, HashArgs h, int* __restrict__ keys,
+                       int* __restrict__ ranks, int* __restrict__ counts, int* __restrict__ flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= h.N) return;
+    int bad = 0;
+    int s[3], c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double w = wrap_coord(pos[3 * (int64_t)i + a], h.L, &bad);
+        s[a] = wrap_index(support_start(w, h.dx, h.MG), h.M);
+        int cc = (int)floor(w / h.cw);
+        c[a] = cc < 0 ? 0 : (cc >= h.m ? h.m - 1 : cc);
+    }
+    if (bad) atomicOr(flag, 1);
+    int bin = s[0] / h.TX + h.nbx * (s[1] / h.TY + h.nby * (s[2] / h.TZ));
+    int cell = c[0] + h.m * (c[1] + h.m * c[2]);
+    keys[i] = bin;
+    keys[h.N + i] = cell;
+    ranks[i] = atomicAdd(&counts[bin], 1);
+    ranks[h.N + i] = atomicAdd(&counts[h.nbins + cell], 1);
+}
+
+// block-wide inclusive scan of one int per thread (blockDim = NT)
+template <int NT>
+__device__ inline int block_inclusive_scan(int v, int* sh) {
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    if (lane == 63) sh[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        int t = lane < NT / 64 ? sh[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < NT / 64; o <<= 1) {
+            int u = __shfl_up(t, o, 64);
+            if (lane >= o) t += u;
+        }
+        if (lane < NT / 64) sh[lane] = t;
+    }
+    __syncthreads();
+    if (wid > 0) v += sh[wid - 1];
+    __syncthreads();
+    return v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* __restrict__ in, int n,
+                                                               int* __restrict__ sums) {
+    __shared__ int sh[kScanThreads / 64];
+    int base = blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    int v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k)
+        if (base + k < n) v += in[base + k];
+    v = block_inclusive_scan<kScanThreads>(v, sh);
+    if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kScanTopThreads) void k_scan_top(int* __restrict__ sums, int nb) {
+    __shared__ int sh[kScanTopThreads / 64];
+    int v = threadIdx.x < nb ? sums[threadIdx.x] : 0;
+    int inc = block_inclusive_scan<kScanTopThreads>(v, sh);
+    if (threadIdx.x < nb) sums[threadIdx.x] = inc - v;     // exclusive
+    if (threadIdx.x == kScanTopThreads - 1) sums[nb] = inc;  // total
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int* __restrict__ in, int n,
+                                                             const int* __restrict__ sums,
+                                                             int* __restrict__ out, int nb) {
+    __shared__ int sh[kScanThreads / 64];
+    int base = blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    int loc[kScanPerThread];
+    int v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        loc[k] = (base + k < n) ? in[base + k] : 0;
+        v += loc[k];
+    }
+    int inc = block_inclusive_scan<kScanThreads>(v, sh);
+    int run = sums[blockIdx.x] + inc - v;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += loc[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
+}
+
+__global__ void k_scatter(const int* __restrict__ keys, const int* __restrict__ ranks,
+                          const int* __restrict__ start_bin, const int* __restrict__ start_cell,
+                          int* __restrict__ perm, int N) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    perm[start_bin[keys[i]] + ranks[i]] = i;
+    perm[N + start_cell[keys[N + i]] + ranks[N + i]] = i;
+}
+
+// order each segment [start[s], start[s+1]) of perm by value (insertion sort)
+__global__ void k_segment_order(const int* __restrict__ start, int nseg, int* __restrict__ perm) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    int b = start[s], e = start[s + 1];
+    for (int i = b + 1; i < e; ++i) {
+        int v = perm[i];
+        int j = i - 1;
+        while (j >= b && perm[j] > v) {
+            perm[j + 1] = perm[j];
+            --j;
+        }
+        perm[j + 1] = v;
+    }
+}
+
+template <typename R>
+__global__ void k_gather_grid(const double* __restrict__ pos, const double* __restrict__ F,
+                              const double* __restrict__ T, const int* __restrict__ perm, int N,
+                              int M, int MG, double L, double dx, double normF, double normT,
+                              GridRec<R>* __restrict__ rec) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    int i = perm[j];
+    int bad = 0;
+    GridRec<R> r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double w = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
+        double u = w / dx;
+        int su = support_start(w, dx, MG);
+        r.s[a] = wrap_index(su, M);
+        r.f[a] = (R)(u - (double)su);
+        r.F[a] = F ? (R)(F[3 * (int64_t)i + a] * normF) : (R)0;
+        r.T[a] = T ? (R)(T[3 * (int64_t)i + a] * normT) : (R)0;
+    }
+    r.orig = i;
+    rec[j] = r;
+}
+
+__global__ void k_gather_pair(const double* __restrict__ pos, const double* __restrict__ F,
+                              const double* __restrict__ T, const int* __restrict__ perm,
+                              const int* __restrict__ cellkey, int N, double L,
+                              PairRec* __restrict__ rec) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    int i = perm[j];
+    int bad = 0;
+    PairRec r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.y[a] = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
+        r.F[a] = F[3 * (int64_t)i + a];
+        r.T[a] = T ? T[3 * (int64_t)i + a] : 0.0;
+    }
+    r.orig = i;
+    r.cell = cellkey[i];
+    rec[j] = r;
+}
+
+inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_fill(int* p, int n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash(const fcm_plan_impl* P, const double* pos, hipStream_t st) {
+    HashArgs h;
+    h.N = (int)P->N;
+    h.M = P->M;
+    h.MG = P->MG;
+    h.TX = P->TX;
+    h.TY = P->TY;
+    h.TZ = P->TZ;
+    h.nbx = P->nbx;
+    h.nby = P->nby;
+    h.nbz = P->nbz;
+    h.nbins = P->nbins;
+    h.m = P->m;
+    h.L = P->L;
+    h.dx = P->dx;
+    h.cw = P->L / P->m;
+    hipLaunchKernelGGL(k_hash, dim3(blocks_for(h.N, 256)), dim3(256), 0, st, pos, h, P->keys,
+                       P->ranks, P->counts, P->flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const int* counts, int* starts, int n, int* tmp, hipStream_t st) {
+    int nb = blocks_for(n, kScanTile);
+    if (nb > kScanTopThreads) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, counts, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, st, tmp, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, counts, n, tmp, starts, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const fcm_plan_impl* P, hipStream_t st) {
+    int N = (int)P->N;
+    const int* sb = P->starts;
+    const int* sc = P->starts + P->nbins + 1;
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(N, 256)), dim3(256), 0, st, P->keys, P->ranks, sb,
+                       sc, P->perm, N);
+    hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(P->nbins, 256)), dim3(256), 0, st, sb,
+                       P->nbins, P->perm);
+    hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(P->ncells, 256)), dim3(256), 0, st, sc,
+                       P->ncells, P->perm + N);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_grid(const fcm_plan_impl* P, const double* pos, const double* F,
+                              const double* T, hipStream_t st) {
+    int N = (int)P->N;
+    const double pi = 3.14159265358979323846;
+    double normF = pow(2.0 * pi * P->Sigma * P->Sigma, -1.5);
+    double normT = pow(2.0 * pi * P->SigmaD * P->SigmaD, -1.5) / (2.0 * P->SigmaD * P->SigmaD);
+    if (P->precision == FCM_FP64)
+        hipLaunchKernelGGL(k_gather_grid<double>, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos,
+                           F, T, P->perm, N, P->M, P->MG, P->L, P->dx, normF, normT,
+                           (GridRec<double>*)P->grec);
+    else
+        hipLaunchKernelGGL(k_gather_grid<float>, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos,
+                           F, T, P->perm, N, P->M, P->MG, P->L, P->dx, normF, normT,
+                           (GridRec<float>*)P->grec);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const double* F,
+                              const double* T, hipStream_t st) {
+    int N = (int)P->N;
+    hipLaunchKernelGGL(k_gather_pair, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, F, T,
+                       P->perm + N, P->keys + N, N, P->L, P->prec);
+    return hipGetLastError();
+}
+
+}  // namespace fcm

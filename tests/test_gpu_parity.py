@@ -1,0 +1,183 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: FP64 plans within 1e-10 normwise relative (elementwise checks too);
+FP32-bulk plans within 1e-5 normwise relative.  Each operator of the path is
+checked on its own (spread, Stokes solve, interpolation, correction) and the
+whole mobility end to end, on grids that span several tiles and ragged
+tilings (grid sizes with factors of 3, odd supports), wrapped positions,
+torques on and off, a separate torque width, standard FCM, and N = 1.
+"""
+
+import math
+import zlib
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_common import (dev, eps_mean, gpu_to_oracle_grid, host, make_plan, maxrel, normwise,
+                        oracle_params, oracle_to_gpu_grid)
+from oracle import fastfcm as ff
+
+pytestmark = pytest.mark.gpu
+
+A = 1.0
+SIG = A / math.sqrt(math.pi)
+
+
+def _case(name):
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    if name == "small":
+        return workloads.workload(0), None
+    if name == "ragged54":
+        L, N = 30.0, 37
+        Y = workloads.rsa_positions(N, L, A, rng)
+        Y[:5] += L * np.array([[-1.0], [1.0], [2.0], [-3.0], [0.0]])   # outside the box
+        w = dict(N=N, L=L, a=A, eta=1.0, grid=54, Sigma=1.3 * L / 54, M_G=9, R_c=7.0,
+                 Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+        return w, None
+    if name == "wideTorque36":
+        L, N = 24.0, 50
+        Y = workloads.rsa_positions(N, L, A, rng)
+        w = dict(N=N, L=L, a=A, eta=0.7, grid=36, Sigma=1.1, M_G=16, R_c=8.0,
+                 Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+        return w, 1.5
+    if name == "standard48":
+        L, N = 20.0, 40
+        Y = workloads.rsa_positions(N, L, A, rng)
+        w = dict(N=N, L=L, a=A, eta=1.0, grid=48, Sigma=SIG, M_G=14, R_c=0.0,
+                 Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+        return w, None
+    if name == "single":
+        w = dict(N=1, L=16.0, a=A, eta=1.0, grid=24, Sigma=2 * SIG, M_G=12, R_c=7.5,
+                 Y=np.array([[15.9, 0.01, 8.0]]), F=np.array([[1.0, -2.0, 0.5]]),
+                 T=np.array([[0.3, 0.2, -1.0]]))
+        return w, None
+    raise KeyError(name)
+
+
+CASES = ["small", "ragged54", "wideTorque36", "standard48", "single"]
+PREC = {"fp64": (0, 1e-10), "fp32": (1, 1e-5)}
+
+
+@pytest.fixture(scope="module", params=CASES)
+def case(request):
+    w, SD = _case(request.param)
+    p = oracle_params(w, Sigma_D=SD)
+    f = ff.spread(p, w["Y"], w["F"], w["T"])
+    u = ff.stokes_solve(p, f)
+    V, W = ff.interp(p, w["Y"], u)
+    dV, dW = ff.pair_correction(p, w["Y"], w["F"], w["T"])
+    return dict(name=request.param, w=w, SD=SD, p=p, f=f, u=u, Vg=V, Wg=W, dV=dV, dW=dW,
+                V=V + dV, W=W + dW)
+
+
+def _plan(c, prec):
+    return make_plan(c["w"], PREC[prec][0], sigma_D_grid=c["SD"] or 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_spread_matches_oracle(case, prec):
+    w = case["w"]
+    plan = _plan(case, prec)
+    g = plan.spread(dev(w["Y"]), dev(w["F"]), dev(w["T"]))
+    got = gpu_to_oracle_grid(host(g).astype(np.float64))
+    tol = PREC[prec][1]
+    assert maxrel(got, case["f"]) < tol, (case["name"], prec, maxrel(got, case["f"]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_matches_oracle(case, prec):
+    import torch
+    plan = _plan(case, prec)
+    g = torch.as_tensor(oracle_to_gpu_grid(case["f"]), device="cuda").to(plan.grid_dtype).contiguous()
+    plan.solve(g)
+    got = gpu_to_oracle_grid(host(g).astype(np.float64))
+    assert normwise(got, case["u"]) < PREC[prec][1], (case["name"], prec, normwise(got, case["u"]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_interp_matches_oracle(case, prec):
+    import torch
+    w = case["w"]
+    plan = _plan(case, prec)
+    g = torch.as_tensor(oracle_to_gpu_grid(case["u"]), device="cuda").to(plan.grid_dtype).contiguous()
+    V, W = plan.interp(dev(w["Y"]), g)
+    tol = PREC[prec][1]
+    assert normwise(host(V), case["Vg"]) < tol
+    assert normwise(host(W), case["Wg"]) < tol
+
+
+def test_correct_matches_oracle(case):
+    w = case["w"]
+    plan = _plan(case, "fp64")
+    import torch
+    V = torch.zeros((w["N"], 3), dtype=torch.float64, device="cuda")
+    W = torch.zeros_like(V)
+    plan.correct(dev(w["Y"]), dev(w["F"]), dev(w["T"]), V, W)
+    for got, ref in ((host(V), case["dV"]), (host(W), case["dW"])):
+        scale = max(np.abs(ref).max(), 1e-300)
+        assert np.abs(got - ref).max() < 1e-12 * scale + 1e-16, (case["name"], np.abs(got - ref).max(), scale)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mobility_matches_oracle(case, prec):
+    w = case["w"]
+    plan = _plan(case, prec)
+    V, W = plan.mobility(dev(w["Y"]), dev(w["F"]), dev(w["T"]))
+    tol = PREC[prec][1]
+    Vh, Wh = host(V), host(W)
+    assert normwise(Vh, case["V"]) < tol, (case["name"], prec, normwise(Vh, case["V"]))
+    assert normwise(Wh, case["W"]) < tol, (case["name"], prec, normwise(Wh, case["W"]))
+    if prec == "fp64":
+        assert maxrel(Vh, case["V"]) < 1e-9 and maxrel(Wh, case["W"]) < 1e-9
+    assert plan.last_error() == 0
+
+
+def test_optional_torque_and_omega(case):
+    """T = NULL means zero torques; Omega = NULL skips angular velocities."""
+    w = case["w"]
+    p = case["p"]
+    plan = _plan(case, "fp64")
+    V, W = plan.mobility(dev(w["Y"]), dev(w["F"]), None)
+    Vr, Wr = ff.mobility(p, w["Y"], w["F"], None)
+    assert normwise(host(V), Vr) < 1e-10 and normwise(host(W), Wr) < 1e-10
+    V2, W2 = plan.mobility(dev(w["Y"]), dev(w["F"]), dev(w["T"]), want_omega=False)
+    assert W2 is None and normwise(host(V2), case["V"]) < 1e-10
+
+
+def test_deterministic_and_permutation_invariant():
+    w = workloads.workload(0)
+    plan = make_plan(w, 0)
+    Y, F, T = dev(w["Y"]), dev(w["F"]), dev(w["T"])
+    V1, W1 = plan.mobility(Y, F, T)
+    V2, W2 = plan.mobility(Y, F, T)
+    assert np.array_equal(host(V1), host(V2)) and np.array_equal(host(W1), host(W2))
+    perm = np.random.default_rng(5).permutation(w["N"])
+    V3, W3 = plan.mobility(dev(w["Y"][perm]), dev(w["F"][perm]), dev(w["T"][perm]))
+    assert maxrel(host(V3), host(V1)[perm]) < 1e-12 and maxrel(host(W3), host(W1)[perm]) < 1e-12
+
+
+def test_spread_interp_adjoint_on_gpu():
+    """<u, J~^dagger F + N~^dagger T> = <(F, T), (J~ u, N~ u)> (Sec. 2: spreading
+    and interpolation are adjoint) for the FP64 HIP operators."""
+    import torch
+    w, _ = _case("ragged54")
+    plan = make_plan(w, 0)
+    rng = np.random.default_rng(8)
+    u = rng.normal(size=(3, w["grid"], w["grid"], w["grid"]))
+    g = plan.spread(dev(w["Y"]), dev(w["F"]), dev(w["T"]))
+    lhs = float(np.sum(host(g) * u)) * (w["L"] / w["grid"]) ** 3
+    V, W = plan.interp(dev(w["Y"]), torch.as_tensor(u, device="cuda").contiguous())
+    rhs = float(np.sum(host(V) * w["F"]) + np.sum(host(W) * w["T"]))
+    assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), 1.0)
+
+
+def test_nonfinite_position_is_reported():
+    w = workloads.workload(0)
+    plan = make_plan(w, 1)
+    Y = w["Y"].copy()
+    Y[3, 1] = np.nan
+    plan.mobility(dev(Y), dev(w["F"]), dev(w["T"]))
+    assert plan.last_error() == -5
+    assert plan.last_error() == 0
