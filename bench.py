@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 path")
     ap.add_argument("--cpu-sample", type=int, default=1000)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="before timing, copy a field-sized device buffer 3 times (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -114,7 +117,9 @@ def cpu_baseline(w, n_sample, V_gpu, W_gpu):
     interpolation and pair correction are timed on a seeded subsample and scaled
     to N.  Also returns the GPU error against the oracle on the subsample."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import fastfcm as ff
+    threadpool_limits(1)
     p = ff.Params(L=w["L"], M=w["grid"], a=w["a"], Sigma=w["Sigma"], M_G=w["M_G"], R_c=w["R_c"])
     N = w["N"]
     rng = np.random.default_rng(12345)
@@ -166,6 +171,14 @@ def main():
     W = torch.empty_like(V)
     mk = lambda prec: Plan(N, w["L"], w["a"], w["Sigma"], w["grid"], w["R_c"], support=w["M_G"],
                            precision=prec)
+    if args.copy_calib:
+        src = torch.ones(3 * w["grid"] ** 3, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {src.numel() * 4} bytes")
+        del src, dst
     plan32 = mk(FCM_FP32_BULK)
     r32 = time_path(plan32, args, Y, F, T, V, W, torch)
     log(f"[bench] fp32 {r32['ms_per_step']:.3f} ms/step  stages {r32['stages_ms']}")

@@ -139,7 +139,7 @@ void free_plan(fcm_plan_impl* P) {
     if (!P) return;
     free_events(P);
     void* bufs[] = {P->grid, P->twid, P->counts, P->starts, P->keys, P->ranks,
-                    P->perm, P->scan_tmp, P->grec, P->prec, P->flag};
+                    P->perm, P->scan_tmp, P->grec, P->prec, P->ppos, P->flag};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete P;
@@ -187,7 +187,7 @@ int fcm_plan_footprint(int64_t N, int grid, int precision, int64_t* bytes) {
     int64_t b = 3 * M * M * M * rs;                     // field / spectrum
     b += M * 2 * rs;                                    // twiddles
     b += 6 * N * (int64_t)sizeof(int);                  // keys, ranks, perm
-    b += N * (int64_t)(grid_rec_size(precision) + sizeof(PairRec));
+    b += N * (int64_t)(grid_rec_size(precision) + sizeof(PairRec) + sizeof(double4));
     const int64_t nbins_max = (M / 2) * (M / 2) * (M / 2);
     const int64_t cells = (int64_t)kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis;
     b += 2 * (nbins_max + 1) * (int64_t)sizeof(int) + 2 * (cells + 1) * (int64_t)sizeof(int);
@@ -307,6 +307,7 @@ int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_del
     FCM_ALLOC(P->scan_tmp, 2048 * sizeof(int));
     FCM_ALLOC(P->grec, (size_t)N * grid_rec_size(P->precision));
     FCM_ALLOC(P->prec, (size_t)N * sizeof(PairRec));
+    FCM_ALLOC(P->ppos, (size_t)N * sizeof(double4));
     FCM_ALLOC(P->flag, 16 * sizeof(int));
 #undef FCM_ALLOC
     if (e != hipSuccess) {

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_r2c(R* __restrict__ grid,
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
     C2<R>* buf = tw + M;
     const int H = M / 2, sw = H + 1;
-    const int line0 = blockIdx.x * Wx;
+    const int line0 = xcd_remap(blockIdx.x, gridDim.x) * Wx;
     C2<R>* g = reinterpret_cast<C2<R>*>(grid);
     load_twiddles(tw, twg, M);
     for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_c2r(R* __restrict__ grid,
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
     C2<R>* buf = tw + M;
     const int H = M / 2, sw = H + 1;
-    const int line0 = blockIdx.x * Wx;
+    const int line0 = xcd_remap(blockIdx.x, gridDim.x) * Wx;
     C2<R>* g = reinterpret_cast<C2<R>*>(grid);
     load_twiddles(tw, twg, M);
     for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
@@ -262,8 +262,9 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_y(C2<R>* __restrict__ spec,
     C2<R>* buf = tw + M;
     const int H = M / 2;
     const int ng = (H + W - 1) / W;
-    const int g = blockIdx.x % ng;
-    const int rest = blockIdx.x / ng;  // c * M + z
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = blk % ng;
+    const int rest = blk / ng;  // c * M + z
     const int kx0 = g * W;
     const int Wv = min(W, H - kx0);
     C2<R>* base = spec + (size_t)rest * M * H + kx0;
@@ -295,8 +296,9 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__
     C2<R>* buf = tw + M;  // 3 components, each M x W
     const int H = M / 2;
     const int ng = (H + W - 1) / W;
-    const int g = blockIdx.x % ng;
-    const int y = blockIdx.x / ng;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = blk % ng;
+    const int y = blk / ng;
     const int kx0 = g * W;
     const int Wv = min(W, H - kx0);
     const size_t cstride = (size_t)M * M * H;

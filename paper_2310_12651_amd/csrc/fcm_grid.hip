@@ -59,13 +59,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
     ZTab<R>* zt = reinterpret_cast<ZTab<R>*>(smem + kChunk * sizeof(GridRec<R>));
 
     const int lane = threadIdx.x;
-    int tile = blockIdx.x;
-    if (a.remap8) {
-        // consecutive workgroups go to different XCDs; give each XCD a
-        // contiguous run of tiles so neighbouring tiles share its L2
-        const int per = gridDim.x >> 3;
-        tile = (tile & 7) * per + (tile >> 3);
-    }
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int M = a.M, MG = a.MG;
     const int btx = tile % a.nbx;
     const int rem = tile / a.nbx;
@@ -214,7 +208,7 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
     __shared__ ZTab<R> zt[4][kMaxSupport];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + wave;
+    const int p = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
     const bool live = p < a.N;
     const GridRec<R> r = rec[live ? p : a.N - 1];
     const int M = a.M, MG = a.MG;

@@ -20,6 +20,16 @@ struct C2 {
     R x, y;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with
+// its own L2.  Map the b-th dispatched block of nb to a logical block so that
+// every XCD receives one contiguous run of logical blocks: neighbouring work
+// (sorted particles, adjacent grid columns) then shares one L2.
+__device__ inline int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, l = b >> 3;
+    return x * q + (x < r ? x : r) + l;
+}
+
 // Per-particle record of the grid kernels, in grid-bin order.  s[] is the
 // first support point along each axis (mod M), f[] the particle coordinate in
 // grid units minus the unwrapped first support point (so the displacement of
@@ -104,6 +114,7 @@ struct fcm_plan_impl {
     int* scan_tmp;         // block sums of the scan
     void* grec;            // N GridRec
     fcm::PairRec* prec;    // N PairRec
+    double4* ppos;         // N wrapped positions in pair order (w unused)
     int* flag;             // [0] = non-finite position seen
     hipStream_t last_stream;
     int sorted_valid;

@@ -83,19 +83,71 @@ __device__ inline Coef correction_coeffs(double r, const PairArgs& a) {
     return c;
 }
 
-__global__ __launch_bounds__(256) void k_pair(const PairRec* __restrict__ rec,
-                                              const int* __restrict__ cell_start, PairArgs a,
-                                              double* __restrict__ V, double* __restrict__ W) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kPairThreads = 256;
+constexpr int kHitBuf = 16;
+
+// add the corrections from one neighbour m at x = Y_n - Y_m (r^2 = r2 < R_c^2)
+__device__ inline void add_pair(double x0, double x1, double x2, double r2, const PairRec& o,
+                                const PairArgs& a, double* v, double* w) {
+    const double F0 = o.F[0], F1 = o.F[1], F2 = o.F[2];
+    const double T0 = o.T[0], T1 = o.T[1], T2 = o.T[2];
+    const double r = sqrt(r2);
+    if (r < 1e-3 * a.sigma) {
+        // coincident centres: the r -> 0 limits (App. B)
+        v[0] += a.selfVF * F0;
+        v[1] += a.selfVF * F1;
+        v[2] += a.selfVF * F2;
+        w[0] += a.selfOT * T0;
+        w[1] += a.selfOT * T1;
+        w[2] += a.selfOT * T2;
+        return;
+    }
+    const Coef c = correction_coeffs(r, a);
+    const double h0 = x0 / r, h1 = x1 / r, h2 = x2 / r;
+    const double hF = h0 * F0 + h1 * F1 + h2 * F2;
+    const double hT = h0 * T0 + h1 * T1 + h2 * T2;
+    // V += Avf F + Bvf xh (xh.F) + fof (T x x)
+    v[0] += c.Avf * F0 + c.Bvf * h0 * hF + c.fof * (T1 * x2 - T2 * x1);
+    v[1] += c.Avf * F1 + c.Bvf * h1 * hF + c.fof * (T2 * x0 - T0 * x2);
+    v[2] += c.Avf * F2 + c.Bvf * h2 * hF + c.fof * (T0 * x1 - T1 * x0);
+    // Omega += fof (F x x) + Aot T + Bot xh (xh.T)
+    w[0] += c.fof * (F1 * x2 - F2 * x1) + c.Aot * T0 + c.Bot * h0 * hT;
+    w[1] += c.fof * (F2 * x0 - F0 * x2) + c.Aot * T1 + c.Bot * h1 * hT;
+    w[2] += c.fof * (F0 * x1 - F1 * x0) + c.Aot * T2 + c.Bot * h2 * hT;
+}
+
+// The candidate scan touches only the compact positions; the pairs found are
+// buffered per lane and evaluated together, so the expensive FP64 body runs
+// with the wavefront converged instead of once per candidate position.
+__global__ __launch_bounds__(kPairThreads) void k_pair(const double4* __restrict__ pos4,
+                                                       const PairRec* __restrict__ rec,
+                                                       const int* __restrict__ cell_start,
+                                                       PairArgs a, double* __restrict__ V,
+                                                       double* __restrict__ W) {
+    __shared__ int hits[kPairThreads][kHitBuf + 1];
+    const int j = xcd_remap(blockIdx.x, gridDim.x) * kPairThreads + threadIdx.x;
     if (j >= a.N) return;
+    int* hb = hits[threadIdx.x];
     const PairRec me = rec[j];
-    double v0 = a.selfVF * me.F[0], v1 = a.selfVF * me.F[1], v2 = a.selfVF * me.F[2];
-    double w0 = a.selfOT * me.T[0], w1 = a.selfOT * me.T[1], w2 = a.selfOT * me.T[2];
+    const double4 mp = pos4[j];
+    double v[3] = {a.selfVF * me.F[0], a.selfVF * me.F[1], a.selfVF * me.F[2]};
+    double w[3] = {a.selfOT * me.T[0], a.selfOT * me.T[1], a.selfOT * me.T[2]};
+    const double L = a.L, iL = 1.0 / a.L;
+    auto flush = [&](int n) {
+        for (int h = 0; h < n; ++h) {
+            const int q = hb[h];
+            const double4 op = pos4[q];
+            double x0 = mp.x - op.x, x1 = mp.y - op.y, x2 = mp.z - op.z;
+            x0 -= L * rint(x0 * iL);
+            x1 -= L * rint(x1 * iL);
+            x2 -= L * rint(x2 * iL);
+            add_pair(x0, x1, x2, x0 * x0 + x1 * x1 + x2 * x2, rec[q], a, v, w);
+        }
+    };
     if (a.with_pairs) {
         const int m = a.m;
         const int cx = me.cell % m, cy = (me.cell / m) % m, cz = me.cell / (m * m);
-        const double L = a.L, iL = 1.0 / a.L;
-        const double rmin = 1e-3 * a.sigma;
+        int nh = 0;
         for (int oz = -1; oz <= 1; ++oz) {
             int nz = cz + oz;
             nz = nz < 0 ? nz + m : (nz >= m ? nz - m : nz);
@@ -108,52 +160,33 @@ __global__ __launch_bounds__(256) void k_pair(const PairRec* __restrict__ rec,
                     const int nc = nx + m * (ny + m * nz);
                     const int b = cell_start[nc], e = cell_start[nc + 1];
                     for (int q = b; q < e; ++q) {
-                        if (q == j) continue;
-                        const PairRec& o = rec[q];
-                        double x0 = me.y[0] - o.y[0], x1 = me.y[1] - o.y[1], x2 = me.y[2] - o.y[2];
+                        const double4 op = pos4[q];
+                        double x0 = mp.x - op.x, x1 = mp.y - op.y, x2 = mp.z - op.z;
                         x0 -= L * rint(x0 * iL);
                         x1 -= L * rint(x1 * iL);
                         x2 -= L * rint(x2 * iL);
                         const double r2 = x0 * x0 + x1 * x1 + x2 * x2;
-                        if (r2 >= a.rc2) continue;
-                        const double r = sqrt(r2);
-                        const double F0 = o.F[0], F1 = o.F[1], F2 = o.F[2];
-                        const double T0 = o.T[0], T1 = o.T[1], T2 = o.T[2];
-                        if (r < rmin) {
-                            // coincident centres: the r -> 0 limits (App. B)
-                            v0 += a.selfVF * F0;
-                            v1 += a.selfVF * F1;
-                            v2 += a.selfVF * F2;
-                            w0 += a.selfOT * T0;
-                            w1 += a.selfOT * T1;
-                            w2 += a.selfOT * T2;
-                            continue;
+                        if (q != j && r2 < a.rc2) {
+                            hb[nh++] = q;
+                            if (nh == kHitBuf) {
+                                flush(nh);
+                                nh = 0;
+                            }
                         }
-                        const Coef c = correction_coeffs(r, a);
-                        const double h0 = x0 / r, h1 = x1 / r, h2 = x2 / r;
-                        const double hF = h0 * F0 + h1 * F1 + h2 * F2;
-                        const double hT = h0 * T0 + h1 * T1 + h2 * T2;
-                        // V += Avf F + Bvf xh (xh.F) + fof (T x x)
-                        v0 += c.Avf * F0 + c.Bvf * h0 * hF + c.fof * (T1 * x2 - T2 * x1);
-                        v1 += c.Avf * F1 + c.Bvf * h1 * hF + c.fof * (T2 * x0 - T0 * x2);
-                        v2 += c.Avf * F2 + c.Bvf * h2 * hF + c.fof * (T0 * x1 - T1 * x0);
-                        // Omega += fof (F x x) + Aot T + Bot xh (xh.T)
-                        w0 += c.fof * (F1 * x2 - F2 * x1) + c.Aot * T0 + c.Bot * h0 * hT;
-                        w1 += c.fof * (F2 * x0 - F0 * x2) + c.Aot * T1 + c.Bot * h1 * hT;
-                        w2 += c.fof * (F0 * x1 - F1 * x0) + c.Aot * T2 + c.Bot * h2 * hT;
                     }
                 }
             }
         }
+        flush(nh);
     }
     const int64_t n = me.orig;
-    V[3 * n + 0] += v0;
-    V[3 * n + 1] += v1;
-    V[3 * n + 2] += v2;
+    V[3 * n + 0] += v[0];
+    V[3 * n + 1] += v[1];
+    V[3 * n + 2] += v[2];
     if (W) {
-        W[3 * n + 0] += w0;
-        W[3 * n + 1] += w1;
-        W[3 * n + 2] += w2;
+        W[3 * n + 0] += w[0];
+        W[3 * n + 1] += w[1];
+        W[3 * n + 2] += w[2];
     }
 }
 
@@ -175,8 +208,8 @@ hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torq
     a.selfVF = P->selfVF;
     a.selfOT = P->selfOT;
     a.with_pairs = P->rc > 0.0 ? 1 : 0;
-    hipLaunchKernelGGL(k_pair, dim3((a.N + 255) / 256), dim3(256), 0, st, P->prec,
-                       P->starts + P->nbins + 1, a, V, W);
+    hipLaunchKernelGGL(k_pair, dim3((a.N + kPairThreads - 1) / kPairThreads), dim3(kPairThreads), 0,
+                       st, P->ppos, P->prec, P->starts + P->nbins + 1, a, V, W);
     return hipGetLastError();
 }
 

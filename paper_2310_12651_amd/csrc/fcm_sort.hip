@@ -201,7 +201,7 @@ __global__ void k_gather_grid(const double* __restrict__ pos, const double* __re
 __global__ void k_gather_pair(const double* __restrict__ pos, const double* __restrict__ F,
                               const double* __restrict__ T, const int* __restrict__ perm,
                               const int* __restrict__ cellkey, int N, double L,
-                              PairRec* __restrict__ rec) {
+                              PairRec* __restrict__ rec, double4* __restrict__ pos4) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     int i = perm[j];
@@ -216,6 +216,7 @@ __global__ void k_gather_pair(const double* __restrict__ pos, const double* __re
     r.orig = i;
     r.cell = cellkey[i];
     rec[j] = r;
+    pos4[j] = make_double4(r.y[0], r.y[1], r.y[2], 0.0);
 }
 
 inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
@@ -292,7 +293,7 @@ hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const d
                               const double* T, hipStream_t st) {
     int N = (int)P->N;
     hipLaunchKernelGGL(k_gather_pair, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, F, T,
-                       P->perm + N, P->keys + N, N, P->L, P->prec);
+                       P->perm + N, P->keys + N, N, P->L, P->prec, P->ppos);
     return hipGetLastError();
 }
 
