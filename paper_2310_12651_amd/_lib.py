@@ -141,7 +141,7 @@ class Plan:
             precision = {"fp64": FCM_FP64, "fp32": FCM_FP32_BULK}[precision]
         o = fcm_options_default()
         o.eta, o.support, o.sigma_D_grid = float(eta), int(support), float(sigma_D_grid)
-        o.precision, o.kahan = int(precision), int(bool(kahan))
+        o.precision, o.kahan = int(precision), int(kahan)
         h = ctypes.c_void_p()
         _check(lib.fcm_plan_ex(ctypes.byref(h), int(N), float(L), float(a), float(Sigma), int(grid),
                                float(r_cut), ctypes.byref(o)), "fcm_plan_ex")

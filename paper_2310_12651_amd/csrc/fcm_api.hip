@@ -64,6 +64,20 @@ RadixPlan make_radix_plan(int n) {
     return rp;
 }
 
+// fill the per-stage strides, divisors and twiddle steps (table length M)
+void finish_radix_plan(RadixPlan& rp, int M) {
+    int Ns = 1;
+    for (int s = 0; s < rp.nst; ++s) {
+        rp.ns[s] = Ns;
+        rp.nsm[s] = div_magic((unsigned)Ns);
+        rp.nb[s] = rp.n / rp.rad[s];
+        rp.nbm[s] = div_magic((unsigned)rp.nb[s]);
+        rp.tstep[s] = M / (Ns * rp.rad[s]);
+        Ns *= rp.rad[s];
+    }
+    rp.nm = div_magic((unsigned)rp.n);
+}
+
 int pow2_floor(int v) {
     int p = 1;
     while (p * 2 <= v) p *= 2;
@@ -255,7 +269,11 @@ int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_del
     P->H = grid / 2;
     P->MG = MG;
     P->precision = opt.precision;
-    P->kahan = opt.kahan ? 1 : 0;
+    if (opt.kahan < 0 || opt.kahan > 2) {
+        delete P;
+        return FCM_EINVAL;
+    }
+    P->kahan = opt.kahan;
     choose_tiles(P);
     int m = 3;
     if (r_cut > 0.0) {
@@ -267,6 +285,8 @@ int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_del
     P->ncells = m * m * m;
     P->radM = make_radix_plan(grid);
     P->radH = make_radix_plan(grid / 2);
+    finish_radix_plan(P->radM, grid);
+    finish_radix_plan(P->radH, grid);
     const int mxy = fft_maxe(P->precision, false) * 256;
     const int mz = fft_maxe(P->precision, true) * 256;
     if (grid > mz) {

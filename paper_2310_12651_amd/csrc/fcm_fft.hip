@@ -100,13 +100,17 @@ struct DFT<R, 8, DIR> {
 
 // One Stockham stage on an LDS tile of W lines of length n; element (w, idx)
 // lives at buf[w * sw + idx * sn].  tw[m] = exp(-2 pi i m / M), n divides M.
+// With wfast the line index w is the fastest-varying thread index (W = 2^lw).
 template <typename R, int RAD, int DIR, int MAXB>
-__device__ void fft_stage(C2<R>* buf, const C2<R>* tw, int M, int n, int Ns, int W, int sw, int sn,
-                          bool wfast) {
-    const int nb = n / RAD;
+__device__ void fft_stage(C2<R>* buf, const C2<R>* tw, const RadixPlan& rp, int s, int W, int lw,
+                          int sw, int sn, bool wfast) {
+    const int nb = rp.nb[s];
+    const unsigned nbm = rp.nbm[s];
+    const int Ns = rp.ns[s];
+    const unsigned nsm = rp.nsm[s];
+    const int tstep = rp.tstep[s];
     const int total = nb * W;
     const int tid = threadIdx.x;
-    const int tstep = M / (Ns * RAD);
     C2<R> v[MAXB][RAD];
     int jj[MAXB], ww[MAXB];
 #pragma unroll
@@ -117,11 +121,11 @@ __device__ void fft_stage(C2<R>* buf, const C2<R>* tw, int M, int n, int Ns, int
         if (t < total) {
             int w, j;
             if (wfast) {
-                w = t % W;
-                j = t / W;
+                w = t & (W - 1);
+                j = t >> lw;
             } else {
-                j = t % nb;
-                w = t / nb;
+                w = fast_div(t, nb, nbm);
+                j = t - w * nb;
             }
             jj[q] = j;
             ww[q] = w;
@@ -135,7 +139,8 @@ __device__ void fft_stage(C2<R>* buf, const C2<R>* tw, int M, int n, int Ns, int
         const int t = tid + q * kFFTThreads;
         if (t < total) {
             const int j = jj[q], w = ww[q];
-            const int k = j % Ns;
+            const int jd = fast_div(j, Ns, nsm);
+            const int k = j - jd * Ns;
 #pragma unroll
             for (int r = 1; r < RAD; ++r) {
                 C2<R> f = tw[r * k * tstep];
@@ -143,7 +148,7 @@ __device__ void fft_stage(C2<R>* buf, const C2<R>* tw, int M, int n, int Ns, int
                 v[q][r] = cmul(v[q][r], f);
             }
             DFT<R, RAD, DIR>::run(v[q]);
-            const int o = (j / Ns) * Ns * RAD + k;
+            const int o = jd * Ns * RAD + k;
 #pragma unroll
             for (int r = 0; r < RAD; ++r) buf[w * sw + (o + r * Ns) * sn] = v[q][r];
         }
@@ -152,18 +157,15 @@ __device__ void fft_stage(C2<R>* buf, const C2<R>* tw, int M, int n, int Ns, int
 }
 
 template <typename R, int DIR, int MAXE>
-__device__ void fft_lines(C2<R>* buf, const C2<R>* tw, int M, const RadixPlan& rp, int W, int sw,
+__device__ void fft_lines(C2<R>* buf, const C2<R>* tw, const RadixPlan& rp, int W, int lw, int sw,
                           int sn, bool wfast) {
-    int Ns = 1;
     for (int s = 0; s < rp.nst; ++s) {
-        const int rad = rp.rad[s];
-        switch (rad) {
-            case 2: fft_stage<R, 2, DIR, (MAXE + 1) / 2>(buf, tw, M, rp.n, Ns, W, sw, sn, wfast); break;
-            case 3: fft_stage<R, 3, DIR, (MAXE + 2) / 3>(buf, tw, M, rp.n, Ns, W, sw, sn, wfast); break;
-            case 4: fft_stage<R, 4, DIR, (MAXE + 3) / 4>(buf, tw, M, rp.n, Ns, W, sw, sn, wfast); break;
-            default: fft_stage<R, 8, DIR, (MAXE + 7) / 8>(buf, tw, M, rp.n, Ns, W, sw, sn, wfast); break;
+        switch (rp.rad[s]) {
+            case 2: fft_stage<R, 2, DIR, (MAXE + 1) / 2>(buf, tw, rp, s, W, lw, sw, sn, wfast); break;
+            case 3: fft_stage<R, 3, DIR, (MAXE + 2) / 3>(buf, tw, rp, s, W, lw, sw, sn, wfast); break;
+            case 4: fft_stage<R, 4, DIR, (MAXE + 3) / 4>(buf, tw, rp, s, W, lw, sw, sn, wfast); break;
+            default: fft_stage<R, 8, DIR, (MAXE + 7) / 8>(buf, tw, rp, s, W, lw, sw, sn, wfast); break;
         }
-        Ns *= rad;
     }
 }
 
@@ -185,13 +187,13 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_r2c(R* __restrict__ grid,
     C2<R>* g = reinterpret_cast<C2<R>*>(grid);
     load_twiddles(tw, twg, M);
     for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
-        const int w = e / H, m = e % H, l = line0 + w;
+        const int w = fast_div(e, H, rpH.nm), m = e - w * H, l = line0 + w;
         buf[w * sw + m] = (l < nlines) ? g[(size_t)l * H + m] : C2<R>{0, 0};
     }
     __syncthreads();
-    fft_lines<R, -1, MAXE>(buf, tw, M, rpH, Wx, sw, 1, false);
+    fft_lines<R, -1, MAXE>(buf, tw, rpH, Wx, 0, sw, 1, false);
     for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
-        const int w = e / H, k = e % H, l = line0 + w;
+        const int w = fast_div(e, H, rpH.nm), k = e - w * H, l = line0 + w;
         if (l >= nlines) continue;
         const C2<R> Z = buf[w * sw + k];
         C2<R> Zc = buf[w * sw + (k == 0 ? 0 : H - k)];
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_c2r(R* __restrict__ grid,
     C2<R>* g = reinterpret_cast<C2<R>*>(grid);
     load_twiddles(tw, twg, M);
     for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
-        const int w = e / H, m = e % H, l = line0 + w;
+        const int w = fast_div(e, H, rpH.nm), m = e - w * H, l = line0 + w;
         buf[w * sw + m] = (l < nlines) ? g[(size_t)l * H + m] : C2<R>{0, 0};
     }
     __syncthreads();
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_c2r(R* __restrict__ grid,
     for (int q = 0; q < MAXE; ++q) {
         const int e = threadIdx.x + q * kFFTThreads;
         if (e < Wx * H) {
-            const int w = e / H, k = e % H;
+            const int w = fast_div(e, H, rpH.nm), k = e - w * H;
             const C2<R> X = buf[w * sw + k];
             C2<R> Xc = {0, 0};
             if (k > 0) {
@@ -242,12 +244,15 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_c2r(R* __restrict__ grid,
 #pragma unroll
     for (int q = 0; q < MAXE; ++q) {
         const int e = threadIdx.x + q * kFFTThreads;
-        if (e < Wx * H) buf[(e / H) * sw + e % H] = zr[q];
+        if (e < Wx * H) {
+            const int w = fast_div(e, H, rpH.nm);
+            buf[w * sw + (e - w * H)] = zr[q];
+        }
     }
     __syncthreads();
-    fft_lines<R, 1, MAXE>(buf, tw, M, rpH, Wx, sw, 1, false);
+    fft_lines<R, 1, MAXE>(buf, tw, rpH, Wx, 0, sw, 1, false);
     for (int e = threadIdx.x; e < Wx * H; e += kFFTThreads) {
-        const int w = e / H, m = e % H, l = line0 + w;
+        const int w = fast_div(e, H, rpH.nm), m = e - w * H, l = line0 + w;
         if (l < nlines) g[(size_t)l * H + m] = buf[w * sw + m];
     }
 }
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_c2r(R* __restrict__ grid,
 template <typename R, int DIR, int MAXE>
 __global__ __launch_bounds__(kFFTThreads) void k_fft_y(C2<R>* __restrict__ spec,
                                                        const C2<R>* __restrict__ twg, int M,
-                                                       RadixPlan rpM, int W) {
+                                                       RadixPlan rpM, int W, int lw) {
     extern __shared__ __align__(16) unsigned char smem[];
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
     C2<R>* buf = tw + M;
@@ -270,13 +275,13 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_y(C2<R>* __restrict__ spec,
     C2<R>* base = spec + (size_t)rest * M * H + kx0;
     load_twiddles(tw, twg, M);
     for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
-        const int w = e % W, y = e / W;
+        const int w = e & (W - 1), y = e >> lw;
         buf[e] = (w < Wv) ? base[(size_t)y * H + w] : C2<R>{0, 0};
     }
     __syncthreads();
-    fft_lines<R, DIR, MAXE>(buf, tw, M, rpM, W, 1, W, true);
+    fft_lines<R, DIR, MAXE>(buf, tw, rpM, W, lw, 1, W, true);
     for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
-        const int w = e % W, y = e / W;
+        const int w = e & (W - 1), y = e >> lw;
         if (w < Wv) base[(size_t)y * H + w] = buf[e];
     }
 }
@@ -290,7 +295,8 @@ struct ProjArgs {
 template <typename R, int MAXE>
 __global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__ spec,
                                                              const C2<R>* __restrict__ twg, int M,
-                                                             RadixPlan rpM, int W, ProjArgs pa) {
+                                                             RadixPlan rpM, int W, int lw,
+                                                             ProjArgs pa) {
     extern __shared__ __align__(16) unsigned char smem[];
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
     C2<R>* buf = tw + M;  // 3 components, each M x W
@@ -306,19 +312,19 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__
     C2<R>* base = spec + (size_t)y * H + kx0;
     load_twiddles(tw, twg, M);
     for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
-        const int w = e % W, z = e / W;
+        const int w = e & (W - 1), z = e >> lw;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             buf[c * M * W + e] = (w < Wv) ? base[c * cstride + (size_t)z * zstride + w] : C2<R>{0, 0};
     }
     __syncthreads();
 #pragma unroll 1
-    for (int c = 0; c < 3; ++c) fft_lines<R, -1, MAXE>(buf + c * M * W, tw, M, rpM, W, 1, W, true);
+    for (int c = 0; c < 3; ++c) fft_lines<R, -1, MAXE>(buf + c * M * W, tw, rpM, W, lw, 1, W, true);
     const R ku = (R)pa.kunit;
     const R sc = (R)pa.scale;
     const int jy = y < H ? y : y - M;
     for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
-        const int w = e % W, z = e / W;
+        const int w = e & (W - 1), z = e >> lw;
         const int jx = kx0 + w;
         const int jz = z < H ? z : z - M;
         const bool zero = (w >= Wv) || (y == H) || (z == H) || (jx == 0 && jy == 0 && jz == 0);
@@ -341,9 +347,9 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__
     }
     __syncthreads();
 #pragma unroll 1
-    for (int c = 0; c < 3; ++c) fft_lines<R, 1, MAXE>(buf + c * M * W, tw, M, rpM, W, 1, W, true);
+    for (int c = 0; c < 3; ++c) fft_lines<R, 1, MAXE>(buf + c * M * W, tw, rpM, W, lw, 1, W, true);
     for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
-        const int w = e % W, z = e / W;
+        const int w = e & (W - 1), z = e >> lw;
         if (w < Wv) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) base[c * cstride + (size_t)z * zstride + w] = buf[c * M * W + e];
@@ -373,18 +379,19 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
     mark(1);
     const int ngy = (H + P->Wy - 1) / P->Wy;
     const size_t shy = (M + (size_t)P->Wy * M) * cs;
+    const int lwy = __builtin_ctz(P->Wy), lwz = __builtin_ctz(P->Wz);
     hipLaunchKernelGGL((k_fft_y<R, -1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec,
-                       tw, M, P->radM, P->Wy);
+                       tw, M, P->radM, P->Wy, lwy);
     mark(2);
     {
         const int ngz = (H + P->Wz - 1) / P->Wz;
         const size_t shz = (M + 3 * (size_t)P->Wz * M) * cs;
         hipLaunchKernelGGL((k_fft_z_solve<R, MZ>), dim3(ngz * M), dim3(kFFTThreads), shz, st, spec,
-                           tw, M, P->radM, P->Wz, pa);
+                           tw, M, P->radM, P->Wz, lwz, pa);
     }
     mark(3);
     hipLaunchKernelGGL((k_fft_y<R, 1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec, tw,
-                       M, P->radM, P->Wy);
+                       M, P->radM, P->Wy, lwy);
     mark(4);
     {
         const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;

@@ -25,7 +25,7 @@ namespace fcm {
 
 namespace {
 
-constexpr int kChunk = 64;
+constexpr int kChunk = 32;
 
 template <typename R>
 struct alignas(16) ZTab {
@@ -35,22 +35,40 @@ struct alignas(16) ZTab {
     R gD;   // Gaussian of width Sigma_D
 };
 
-__device__ inline float fexp2(float x) { return exp2f(x); }
+// 2^x for x <= 0: the hardware exponential (results below the FP32 normal
+// range flush towards 0, which only drops kernel tails beyond ~e^-87)
+__device__ inline float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline double fexp2(double x) { return exp2(x); }
 
-template <bool K, typename R>
-__device__ inline void kadd(R& s, R& c, R v) {
-    if (K) {
-        R y = v - c;
-        R t = s + y;
-        c = (t - s) - y;
-        s = t;
-    } else {
-        s += v;
-    }
-}
+// Accumulation of the spread sums: ACC_PLAIN adds in the grid precision,
+// ACC_KAHAN keeps a Kahan compensation term per value, ACC_WIDE accumulates
+// FP32 contributions in FP64 registers.
+enum { ACC_PLAIN = 0, ACC_KAHAN = 1, ACC_WIDE = 2 };
 
-template <typename R, int TZ, bool KAHAN, bool TORQUE>
+template <int MODE, typename R>
+struct Acc {
+    R s = 0, c = 0;
+    __device__ inline void add(R v) {
+        if (MODE == ACC_KAHAN) {
+            const R y = v - c;
+            const R t = s + y;
+            c = (t - s) - y;
+            s = t;
+        } else {
+            s += v;
+        }
+    }
+    __device__ inline R value() const { return MODE == ACC_KAHAN ? s - c : s; }
+};
+
+template <>
+struct Acc<ACC_WIDE, float> {
+    double s = 0;
+    __device__ inline void add(float v) { s += (double)v; }
+    __device__ inline float value() const { return (float)s; }
+};
+
+template <typename R, int TZ, int MODE, bool TORQUE, bool SAMEW>
 __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ rec,
                                                const int* __restrict__ bin_start,
                                                R* __restrict__ grid, GridArgs<R> a) {
@@ -71,14 +89,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
     const int gxp = X0 + li, gyp = Y0 + (lact ? lj : 0);
     const R dx = a.dx;
 
-    R acc[3][TZ], cmp[3][TZ];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int k = 0; k < TZ; ++k) {
-            acc[c][k] = 0;
-            cmp[c][k] = 0;
-        }
+    Acc<MODE, R> acc[3][TZ];
 
     for (int oz = 0; oz <= a.backz; ++oz) {
         int bz = btz - oz;
@@ -95,7 +106,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                     const int p = base + lane;
                     bool take = false;
                     GridRec<R> r;
-                    if (p < end) {
+                    if (lane < kChunk && p < end) {
                         r = rec[p];
                         int d0x = X0 - r.s[0];
                         if (d0x < 0) d0x += M;
@@ -118,7 +129,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                             e.g = fexp2(-d2 * a.e2);
                             e.d = d;
                             e.d2 = d2;
-                            e.gD = a.same_width ? e.g : fexp2(-d2 * a.e2D);
+                            e.gD = SAMEW ? e.g : fexp2(-d2 * a.e2D);
                             zt[slot * MG + t] = e;
                         }
                     }
@@ -135,16 +146,13 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                         const R dxv = ((R)dxi - stg[q].f[0]) * dx;
                         const R dyv = ((R)dyi - stg[q].f[1]) * dx;
                         const R x2 = dxv * dxv, y2 = dyv * dyv;
-                        const R wx = in ? fexp2(-x2 * a.e2) : (R)0;
-                        const R wy = fexp2(-y2 * a.e2);
-                        const R gxy = wx * wy;
+                        const R gxy = in ? fexp2(-(x2 + y2) * a.e2) : (R)0;
                         const R base_w = gxy * (a.A + a.B * (x2 + y2));
                         const R gB = gxy * a.B;
                         const R F0 = stg[q].F[0], F1 = stg[q].F[1], F2 = stg[q].F[2];
                         R gxyD = gxy, T0 = 0, T1 = 0, ax = 0, ay = 0, az = 0;
                         if (TORQUE) {
-                            if (!a.same_width)
-                                gxyD = in ? fexp2(-x2 * a.e2D) * fexp2(-y2 * a.e2D) : (R)0;
+                            if (!SAMEW) gxyD = in ? fexp2(-(x2 + y2) * a.e2D) : (R)0;
                             T0 = stg[q].T[0];
                             T1 = stg[q].T[1];
                             const R T2 = stg[q].T[2];
@@ -166,13 +174,13 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                                     const R wt = e.gD * gxyD;
                                     const R tx = ax + T1 * e.d;
                                     const R ty = ay - T0 * e.d;
-                                    kadd<KAHAN>(acc[0][k], cmp[0][k], w * F0 + wt * tx);
-                                    kadd<KAHAN>(acc[1][k], cmp[1][k], w * F1 + wt * ty);
-                                    kadd<KAHAN>(acc[2][k], cmp[2][k], w * F2 + wt * az);
+                                    acc[0][k].add(w * F0 + wt * tx);
+                                    acc[1][k].add(w * F1 + wt * ty);
+                                    acc[2][k].add(w * F2 + wt * az);
                                 } else {
-                                    kadd<KAHAN>(acc[0][k], cmp[0][k], w * F0);
-                                    kadd<KAHAN>(acc[1][k], cmp[1][k], w * F1);
-                                    kadd<KAHAN>(acc[2][k], cmp[2][k], w * F2);
+                                    acc[0][k].add(w * F0);
+                                    acc[1][k].add(w * F1);
+                                    acc[2][k].add(w * F2);
                                 }
                             }
                         }
@@ -188,7 +196,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
         for (int k = 0; k < TZ; ++k) {
             const size_t idx = ((size_t)(Z0 + k) * M + gyp) * M + gxp;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) grid[c * M3 + idx] = KAHAN ? acc[c][k] - cmp[c][k] : acc[c][k];
+            for (int c = 0; c < 3; ++c) grid[c * M3 + idx] = acc[c][k].value();
         }
     }
 }
@@ -238,7 +246,7 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
         const R dxv = ((R)i - r.f[0]) * dx;
         const R dyv = ((R)j - r.f[1]) * dx;
         const R x2 = dxv * dxv, y2 = dyv * dyv;
-        const R gxy = ok ? fexp2(-x2 * a.e2) * fexp2(-y2 * a.e2) : (R)0;
+        const R gxy = ok ? fexp2(-(x2 + y2) * a.e2) : (R)0;
         R A0[3] = {0, 0, 0}, A2[3] = {0, 0, 0}, D1[3] = {0, 0, 0}, D0[3] = {0, 0, 0};
         const R* colp = grid + (size_t)y * M + x;
         for (int k = 0; k < MG; ++k) {
@@ -275,7 +283,7 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
             R gD = gxy;
             const R* S0 = A0;
             if (!SAMEW) {
-                gD = ok ? fexp2(-x2 * a.e2D) * fexp2(-y2 * a.e2D) : (R)0;
+                gD = ok ? fexp2(-(x2 + y2) * a.e2D) : (R)0;
                 S0 = D0;
             }
             // (d x u): x: dy u_z - dz u_y ; y: dz u_x - dx u_z ; z: dx u_y - dy u_x
@@ -334,31 +342,35 @@ GridArgs<R> make_args(const fcm_plan_impl* P) {
     return a;
 }
 
-template <typename R, int TZ, bool K>
-hipError_t spread_tz(const fcm_plan_impl* P, bool torque, R* grid, hipStream_t st) {
+template <typename R, int TZ, int MODE, bool TORQUE>
+hipError_t spread_tz(const fcm_plan_impl* P, R* grid, hipStream_t st) {
     GridArgs<R> a = make_args<R>(P);
     const size_t shm = kChunk * (sizeof(GridRec<R>) + (size_t)P->MG * sizeof(ZTab<R>));
     dim3 g(P->nbins), b(64);
-    if (torque)
-        hipLaunchKernelGGL((k_spread<R, TZ, K, true>), g, b, shm, st,
-                           (const GridRec<R>*)P->grec, P->starts, grid, a);
+    const GridRec<R>* rec = (const GridRec<R>*)P->grec;
+    if (a.same_width)
+        hipLaunchKernelGGL((k_spread<R, TZ, MODE, TORQUE, true>), g, b, shm, st, rec, P->starts, grid, a);
     else
-        hipLaunchKernelGGL((k_spread<R, TZ, K, false>), g, b, shm, st,
-                           (const GridRec<R>*)P->grec, P->starts, grid, a);
+        hipLaunchKernelGGL((k_spread<R, TZ, MODE, TORQUE, false>), g, b, shm, st, rec, P->starts, grid, a);
     return hipGetLastError();
 }
 
-template <typename R, bool K>
-hipError_t spread_r(const fcm_plan_impl* P, bool torque, R* grid, hipStream_t st) {
+template <typename R, int MODE, bool TORQUE>
+hipError_t spread_m(const fcm_plan_impl* P, R* grid, hipStream_t st) {
     switch (P->TZ) {
-        case 16: return spread_tz<R, 16, K>(P, torque, grid, st);
-        case 12: return spread_tz<R, 12, K>(P, torque, grid, st);
-        case 8: return spread_tz<R, 8, K>(P, torque, grid, st);
-        case 6: return spread_tz<R, 6, K>(P, torque, grid, st);
-        case 4: return spread_tz<R, 4, K>(P, torque, grid, st);
-        case 2: return spread_tz<R, 2, K>(P, torque, grid, st);
+        case 16: return spread_tz<R, 16, MODE, TORQUE>(P, grid, st);
+        case 12: return spread_tz<R, 12, MODE, TORQUE>(P, grid, st);
+        case 8: return spread_tz<R, 8, MODE, TORQUE>(P, grid, st);
+        case 6: return spread_tz<R, 6, MODE, TORQUE>(P, grid, st);
+        case 4: return spread_tz<R, 4, MODE, TORQUE>(P, grid, st);
+        case 2: return spread_tz<R, 2, MODE, TORQUE>(P, grid, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <typename R, int MODE>
+hipError_t spread_r(const fcm_plan_impl* P, bool torque, R* grid, hipStream_t st) {
+    return torque ? spread_m<R, MODE, true>(P, grid, st) : spread_m<R, MODE, false>(P, grid, st);
 }
 
 template <typename R>
@@ -383,9 +395,10 @@ hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W,
 }  // namespace
 
 hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st) {
-    if (P->precision == FCM_FP64) return spread_r<double, false>(P, torque, (double*)grid, st);
-    if (P->kahan) return spread_r<float, true>(P, torque, (float*)grid, st);
-    return spread_r<float, false>(P, torque, (float*)grid, st);
+    if (P->precision == FCM_FP64) return spread_r<double, ACC_PLAIN>(P, torque, (double*)grid, st);
+    if (P->kahan == 1) return spread_r<float, ACC_KAHAN>(P, torque, (float*)grid, st);
+    if (P->kahan == 2) return spread_r<float, ACC_WIDE>(P, torque, (float*)grid, st);
+    return spread_r<float, ACC_PLAIN>(P, torque, (float*)grid, st);
 }
 
 hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, double* W,

@@ -53,11 +53,30 @@ struct alignas(16) PairRec {
     double T[3];
 };
 
+// A length-n mixed-radix Stockham plan.  Per stage s: radix rad[s], the
+// product ns[s] of the radices before it, the butterflies per line nb[s] =
+// n / rad[s], and the twiddle step tstep[s] = M / (ns[s] rad[s]) into the
+// length-M table.  Divisions by ns and nb use multipliers m = 2^32/d + 1
+// (exact for numerators and divisors below 2^16; d = 1 is special-cased).
 struct RadixPlan {
-    int n;                         // transform length
-    int nst;                       // number of stages
-    int rad[kMaxRadixStages];      // radices in application order
+    int n;                                 // transform length
+    int nst;                               // number of stages
+    int rad[kMaxRadixStages];
+    int ns[kMaxRadixStages];
+    unsigned nsm[kMaxRadixStages];
+    int nb[kMaxRadixStages];
+    unsigned nbm[kMaxRadixStages];
+    int tstep[kMaxRadixStages];
+    unsigned nm;                           // multiplier for division by n
 };
+
+__host__ __device__ inline unsigned div_magic(unsigned d) {
+    return d <= 1 ? 0u : (unsigned)(0x100000000ull / d + 1ull);
+}
+
+__device__ inline int fast_div(int j, int d, unsigned m) {
+    return d == 1 ? j : (int)__umulhi((unsigned)j, m);
+}
 
 // Scalars of the grid kernels (one plan).
 template <typename R>
