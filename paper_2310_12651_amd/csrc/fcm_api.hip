@@ -226,6 +226,7 @@ int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_del
     if (!(L > 0.0) || !isfinite(L) || !(a > 0.0) || !isfinite(a)) return FCM_EINVAL;
     if (!(opt.eta > 0.0) || !isfinite(opt.eta)) return FCM_EINVAL;
     if (opt.precision != FCM_FP64 && opt.precision != FCM_FP32_BULK) return FCM_EINVAL;
+    if (opt.kahan < 0 || opt.kahan > 2) return FCM_EINVAL;
     if (!is_smooth_even(grid)) return FCM_EINVAL;
     const double sigma = a / sqrt(kPi);
     const double sigmaD = a / cbrt(6.0 * sqrt(kPi));
@@ -269,10 +270,6 @@ int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_del
     P->H = grid / 2;
     P->MG = MG;
     P->precision = opt.precision;
-    if (opt.kahan < 0 || opt.kahan > 2) {
-        delete P;
-        return FCM_EINVAL;
-    }
     P->kahan = opt.kahan;
     choose_tiles(P);
     int m = 3;

@@ -1,0 +1,100 @@
+"""The C-ABI library loads, exports every function include/*.h declares, and
+rejects invalid plans before touching a device (no GPU needed)."""
+
+import ctypes
+import glob
+import math
+import os
+import re
+
+import pytest
+
+import paper_2310_12651_amd as fcm
+from paper_2310_12651_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**\s*(fcm_[a-z0-9_]+)\s*\(",
+                             text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libfcm.so not built")
+    return fcm.library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "fcm_mobility" in names and "fcm_plan" in names and len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding wraps exactly the declared calls
+    assert set(_lib.EXPORTS) <= set(names)
+
+
+def test_status_strings_and_defaults(lib):
+    assert fcm.status_string(0) == "ok"
+    assert "cut-off" in fcm.status_string(fcm.FCM_ERANGE)
+    o = fcm.fcm_options_default()
+    assert o.eta == 1.0 and o.support == 0 and o.precision == fcm.FCM_FP32_BULK and o.kahan == 1
+
+
+def _plan(lib, N=10, L=20.0, a=1.0, Sigma=1.0, grid=32, rc=5.0, **kw):
+    o = fcm.fcm_options_default()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    return lib.fcm_plan_ex(ctypes.byref(h), N, L, a, Sigma, grid, rc, ctypes.byref(o))
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(N=0), fcm.FCM_EINVAL),
+    (dict(L=-1.0), fcm.FCM_EINVAL),
+    (dict(a=0.0), fcm.FCM_EINVAL),
+    (dict(Sigma=0.3), fcm.FCM_EINVAL),             # below sigma = a / sqrt(pi)
+    (dict(grid=30), fcm.FCM_EINVAL),               # 30 = 2 * 3 * 5
+    (dict(grid=27), fcm.FCM_EINVAL),               # odd
+    (dict(grid=2048), fcm.FCM_EINVAL),             # too large
+    (dict(rc=10.0), fcm.FCM_ERANGE),               # r_cut >= L/2
+    (dict(rc=-1.0), fcm.FCM_EINVAL),
+    (dict(support=40), fcm.FCM_EINVAL),
+    (dict(grid=16, support=18), fcm.FCM_EINVAL),   # exceeds the grid
+    (dict(eta=0.0), fcm.FCM_EINVAL),
+    (dict(precision=7), fcm.FCM_EINVAL),
+    (dict(kahan=3), fcm.FCM_EINVAL),
+    (dict(sigma_D_grid=0.1), fcm.FCM_EINVAL),      # below sigma_D
+    (dict(L=float("nan")), fcm.FCM_EINVAL),
+])
+def test_plan_validation(lib, kw, code):
+    assert _plan(lib, **kw) == code
+
+
+def test_null_arguments_are_rejected(lib):
+    assert lib.fcm_plan_ex(None, 10, 20.0, 1.0, 1.0, 32, 5.0, None) == fcm.FCM_EINVAL
+    assert lib.fcm_mobility(None, None, None, None, None, None, None) == fcm.FCM_EINVAL
+    assert lib.fcm_plan_destroy(None) == fcm.FCM_EINVAL
+    b = ctypes.c_int64()
+    assert lib.fcm_plan_footprint(0, 32, 1, ctypes.byref(b)) == fcm.FCM_EINVAL
+
+
+def test_footprint_scales_with_grid_and_precision(lib):
+    f32 = fcm.fcm_plan_footprint(100_000, 256, fcm.FCM_FP32_BULK)
+    f64 = fcm.fcm_plan_footprint(100_000, 256, fcm.FCM_FP64)
+    assert f32 > 12 * 256 ** 3 and f64 > 24 * 256 ** 3 and f64 > f32
+    assert fcm.fcm_plan_footprint(1000, 64, 1) < f32
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(fcm.LibraryMissing):
+        _lib.library()
