@@ -7,10 +7,13 @@ volume fraction 10 %, 256^3 grid, Sigma = dx, M_G = 10, R_c = 5.5 Sigma, with
 inputs resident in device memory.  The value is particle-mobility evaluations
 per second (N / seconds per step) of the FP32-bulk path; the FP64 path, call
 latency percentiles, per-stage times, the roofline of the dominant kernel and
-the oracle timed on host cores are reported beside it on the same JSON line.
+the oracle timed on host cores are reported beside it on the same JSON line,
+together with the serving leg: a 512-request mixed-size stream replayed with
+Poisson arrivals through the one-request-at-a-time FP64 path and through the
+continuous-batching FP32-bulk server (p50/p99 latency, throughput).
 
-    python bench.py [--steps K] [--warmup W] [--workload dense|dilute|rods|small]
-                    [--no-cpu] [--no-fp64]
+    python bench.py [--steps K] [--warmup W] [--workload dense|dilute|rods|small|serving]
+                    [--no-cpu] [--no-fp64] [--no-serving] [--requests R]
 """
 
 import argparse
@@ -24,7 +27,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOADS = {"small": 0, "dilute": 1, "dense": 2, "rods": 3}
+WORKLOADS = {"small": 0, "dilute": 1, "dense": 2, "rods": 3, "serving": None}
 HBM_PEAK_GBS = 8000.0
 METRIC = "mobility evals/s (N=1e5, ≤1e-4 rel err) FP32 vs FP64; p50/p99 latency"
 
@@ -38,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 path")
     ap.add_argument("--cpu-sample", type=int, default=1000)
+    ap.add_argument("--requests", type=int, default=512, help="serving stream length")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="before timing, copy a field-sized device buffer 3 times (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -148,6 +153,70 @@ def cpu_baseline(w, n_sample, V_gpu, W_gpu):
     return base, acc
 
 
+def serving_leg(args, torch):
+    """The mixed-size request stream: the one-request-at-a-time FP64 path
+    (closed loop, then Poisson arrivals at 0.8x its throughput) against the
+    continuous-batching FP32-bulk server (8 slots) on the same arrivals."""
+    import numpy as np
+
+    import workloads
+    from paper_2310_12651_amd import FCM_FP32_BULK, FCM_FP64
+    from paper_2310_12651_amd.serving import Server, replay, run_sequential
+    reqs = workloads.serving_stream(args.requests)
+    t = time.perf_counter()
+    dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    tensors = []
+    for r in reqs:
+        Y, F, T = workloads.request_inputs(r)
+        V = torch.empty((r["N"], 3), dtype=torch.float64, device="cuda")
+        tensors.append((dev(Y), dev(F), dev(T), V, torch.empty_like(V)))
+    torch.cuda.synchronize()
+    total = sum(r["N"] for r in reqs)
+    log(f"[bench] serving stream: {len(reqs)} requests, {total} particles, inputs in {time.perf_counter() - t:.1f} s")
+    budget = int(0.35 * torch.cuda.mem_get_info()[0])
+    pct = lambda lat, p: float(np.percentile(np.asarray(lat), p))
+
+    def warm(server):
+        seen = set()
+        for i, r in enumerate(reqs):
+            if r["grid"] not in seen:
+                seen.add(r["grid"])
+                run_sequential(server, [r], [tensors[i]])
+
+    s64 = Server(slots=1, precision=FCM_FP64, max_bytes=budget)
+    warm(s64)
+    _, T_seq = run_sequential(s64, reqs, tensors)
+    rate = 0.8 * len(reqs) / T_seq
+    rng = np.random.default_rng(workloads.SEED_BASE + 5)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+    lat64, mk64 = replay(s64, reqs, tensors, arrivals)
+    st64 = s64.stats()
+    s64.close()
+    log(f"[bench] fp64 one-at-a-time: closed loop {T_seq:.2f} s; Poisson at {rate:.1f}/s: p50 "
+        f"{pct(lat64, 50):.2f} ms p99 {pct(lat64, 99):.2f} ms makespan {mk64:.2f} s")
+    s32 = Server(slots=8, precision=FCM_FP32_BULK, max_bytes=budget)
+    warm(s32)
+    lat32, mk32 = replay(s32, reqs, tensors, arrivals)
+    _, T32 = replay(s32, reqs, tensors, None)
+    st32 = s32.stats()
+    s32.close()
+    log(f"[bench] fp32 server: p50 {pct(lat32, 50):.2f} ms p99 {pct(lat32, 99):.2f} ms makespan "
+        f"{mk32:.2f} s; closed loop {T32:.2f} s")
+    return {
+        "requests": len(reqs), "particles": total, "arrival_rate_per_s": rate,
+        "fp64_one_at_a_time": {"p50_ms": pct(lat64, 50), "p99_ms": pct(lat64, 99),
+                               "throughput_evals_per_s": total / mk64,
+                               "closed_loop_evals_per_s": total / T_seq,
+                               "plans_built": st64["plans_built"], "plans_rebound": st64["plans_rebound"]},
+        "fp32_server_8_slots": {"p50_ms": pct(lat32, 50), "p99_ms": pct(lat32, 99),
+                                "throughput_evals_per_s": total / mk32,
+                                "closed_loop_evals_per_s": total / T32,
+                                "inflight_peak": st32["inflight_peak"], "plans_built": st32["plans_built"],
+                                "plans_rebound": st32["plans_rebound"],
+                                "plans_evicted": st32["plans_evicted"]},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -160,6 +229,10 @@ def main():
     import workloads
     from paper_2310_12651_amd import FCM_FP32_BULK, FCM_FP64, Plan
 
+    if args.workload == "serving":
+        print(json.dumps({"metric": "serving stream p50/p99 latency and throughput", "serving":
+                          serving_leg(args, torch)}), flush=True)
+        return
     wid = WORKLOADS[args.workload]
     t = time.perf_counter()
     w = workloads.workload(wid)
@@ -208,6 +281,9 @@ def main():
                     traffic=tr, algorithmic_bytes=ab, launch_ms=round(stages[dom_grid], 5))
     per_stage_gbs = {s: round(algorithmic_bytes(w, s) / (stages[s] * 1e-3) / 1e9, 1)
                      for s in grid_stages}
+    serving = None
+    if not args.no_serving:
+        serving = serving_leg(args, torch)
     base, acc = None, None
     if not args.no_cpu:
         log("[bench] timing the oracle on the host (bounded sample)")
@@ -238,6 +314,7 @@ def main():
         "accuracy": {"vs_oracle_subsample": acc, "fp32_vs_fp64": acc64},
         "roofline": roof,
         "cpu_baseline": base,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

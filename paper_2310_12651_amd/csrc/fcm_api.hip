@@ -10,10 +10,6 @@
 
 #include "fcm_internal.h"
 
-namespace fcm {
-int fft_maxe(int precision, bool zpass);
-}
-
 using namespace fcm;
 
 namespace {
@@ -182,6 +178,177 @@ bool needs_correction(const fcm_plan_impl* P) {
 
 }  // namespace
 
+namespace fcm {
+
+// Validate the arguments and fill every scalar of a plan (no allocation).
+int plan_derive(fcm_plan_impl* P, int64_t N, double L, double a, double sigma_delta, int grid,
+                double r_cut, const fcm_options* opt_in) {
+    fcm_options opt;
+    fcm_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    if (N <= 0 || N > (int64_t)1 << 29) return FCM_EINVAL;
+    if (!(L > 0.0) || !isfinite(L) || !(a > 0.0) || !isfinite(a)) return FCM_EINVAL;
+    if (!(opt.eta > 0.0) || !isfinite(opt.eta)) return FCM_EINVAL;
+    if (opt.precision != FCM_FP64 && opt.precision != FCM_FP32_BULK) return FCM_EINVAL;
+    if (opt.kahan < 0 || opt.kahan > 2) return FCM_EINVAL;
+    if (!is_smooth_even(grid)) return FCM_EINVAL;
+    const double sigma = a / sqrt(kPi);
+    const double sigmaD = a / cbrt(6.0 * sqrt(kPi));
+    if (!(sigma_delta >= sigma * (1.0 - 1e-12)) || !isfinite(sigma_delta)) return FCM_EINVAL;
+    const double Sigma = sigma_delta < sigma ? sigma : sigma_delta;
+    double SigmaD = opt.sigma_D_grid > 0.0 ? opt.sigma_D_grid : Sigma;
+    if (!(SigmaD >= sigmaD * (1.0 - 1e-12)) || !isfinite(SigmaD)) return FCM_EINVAL;
+    if (SigmaD < sigmaD) SigmaD = sigmaD;
+    if (!(r_cut >= 0.0) || !isfinite(r_cut)) return FCM_EINVAL;
+    if (r_cut >= 0.5 * L) return FCM_ERANGE;
+    const double dx = L / grid;
+    int MG = opt.support;
+    if (MG == 0) {
+        const double wmax = Sigma > SigmaD ? Sigma : SigmaD;
+        MG = (int)ceil(10.0 * wmax / dx - 1e-9);
+        if (MG & 1) ++MG;
+        if (MG < 8) MG = 8;
+    }
+    if (MG < 2 || MG > kMaxSupport || MG > grid) return FCM_EINVAL;
+    // FP64 spreading stages its particles with M_G-point tables in LDS
+    if (opt.precision == FCM_FP64 && MG > 24) return FCM_EINVAL;
+    const int mz = fft_maxe(opt.precision, true) * 256;
+    if (grid > mz) return FCM_EINVAL;
+
+    P->N = N;
+    P->L = L;
+    P->a = a;
+    P->eta = opt.eta;
+    P->sigma = sigma;
+    P->sigmaD = sigmaD;
+    P->Sigma = Sigma;
+    P->SigmaD = SigmaD;
+    P->rc = r_cut;
+    P->dx = dx;
+    P->M = grid;
+    P->H = grid / 2;
+    P->MG = MG;
+    P->precision = opt.precision;
+    P->kahan = opt.kahan;
+    choose_tiles(P);
+    int m = 3;
+    if (r_cut > 0.0) {
+        const double q = L / r_cut;
+        m = q > (double)kMaxCellsPerAxis ? kMaxCellsPerAxis : (int)q;
+        if (m < 3) m = 3;
+    }
+    P->m = m;
+    P->ncells = m * m * m;
+    P->radM = make_radix_plan(grid);
+    P->radH = make_radix_plan(grid / 2);
+    finish_radix_plan(P->radM, grid);
+    finish_radix_plan(P->radH, grid);
+    const int mxy = fft_maxe(P->precision, false) * 256;
+    P->Wy = pow2_floor(mxy / grid);
+    if (P->Wy > 32) P->Wy = 32;
+    P->Wz = pow2_floor(mz / grid);
+    if (P->Wz > 32) P->Wz = 32;
+    P->Wx = mxy / P->H;
+    if (P->Wx > 64) P->Wx = 64;
+    if (P->Wx < 1) P->Wx = 1;
+    {
+        const double sp = Sigma * sqrt(kPi);
+        const double d = sigma * sigma - Sigma * Sigma;
+        P->selfVF = 1.0 / (6.0 * kPi * P->eta * a) - 1.0 / (6.0 * kPi * P->eta * sp) +
+                    d / (12.0 * P->eta * sp * sp * sp) -
+                    d * d / (32.0 * P->eta * pow(Sigma, 5.0) * pow(kPi, 1.5));
+        const double sd = SigmaD * sqrt(kPi);
+        P->selfOT = 1.0 / (8.0 * kPi * P->eta * a * a * a) - 1.0 / (48.0 * P->eta * sd * sd * sd);
+    }
+    return FCM_OK;
+}
+
+// Allocate the device buffers of a derived plan for up to ncap particles and
+// cellcap pair cells, and upload the twiddles.  No device-wide synchronisation.
+int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
+    if (hipGetDevice(&P->device) != hipSuccess) return FCM_EDEVICE;
+    P->Ncap = ncap;
+    P->cells_cap = cellcap;
+    const int grid = P->M;
+    const size_t rs = real_size(P->precision);
+    const size_t M3 = (size_t)grid * grid * grid;
+    hipError_t e = hipSuccess;
+#define FCM_ALLOC(ptr, bytes)                                        \
+    do {                                                             \
+        if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes)); \
+    } while (0)
+    FCM_ALLOC(P->grid, 3 * M3 * rs);
+    FCM_ALLOC(P->twid, (size_t)grid * 2 * rs);
+    FCM_ALLOC(P->counts, (size_t)(P->nbins + cellcap) * sizeof(int));
+    FCM_ALLOC(P->starts, (size_t)(P->nbins + 1 + cellcap + 1) * sizeof(int));
+    FCM_ALLOC(P->keys, (size_t)2 * ncap * sizeof(int));
+    FCM_ALLOC(P->ranks, (size_t)2 * ncap * sizeof(int));
+    FCM_ALLOC(P->perm, (size_t)2 * ncap * sizeof(int));
+    FCM_ALLOC(P->scan_tmp, 2048 * sizeof(int));
+    FCM_ALLOC(P->grec, (size_t)ncap * grid_rec_size(P->precision));
+    FCM_ALLOC(P->prec, (size_t)ncap * sizeof(PairRec));
+    FCM_ALLOC(P->ppos, (size_t)ncap * sizeof(double4));
+    FCM_ALLOC(P->flag, 16 * sizeof(int));
+#undef FCM_ALLOC
+    if (e != hipSuccess) return map_err(e);
+    // twiddles exp(-2 pi i m / M) in extended precision, rounded once
+    const size_t n = (size_t)grid * 2;
+    void* host = malloc(n * rs);
+    if (!host) return FCM_ENOMEM;
+    for (int mm = 0; mm < grid; ++mm) {
+        const long double ang = -2.0L * 3.141592653589793238462643383279502884L * mm / grid;
+        const long double c = cosl(ang), sn = sinl(ang);
+        if (P->precision == FCM_FP64) {
+            ((double*)host)[2 * mm] = (double)c;
+            ((double*)host)[2 * mm + 1] = (double)sn;
+        } else {
+            ((float*)host)[2 * mm] = (float)c;
+            ((float*)host)[2 * mm + 1] = (float)sn;
+        }
+    }
+    e = hipMemcpy(P->twid, host, n * rs, hipMemcpyHostToDevice);
+    free(host);
+    if (e == hipSuccess) e = hipMemset(P->flag, 0, 16 * sizeof(int));
+    return map_err(e);
+}
+
+// Re-parameterise an allocated plan with the scalars of `d` (derived for a new
+// problem of the same grid, support, precision and accumulation mode).
+int plan_rebind(fcm_plan_impl* P, const fcm_plan_impl* d) {
+    if (d->M != P->M || d->MG != P->MG || d->precision != P->precision || d->kahan != P->kahan ||
+        d->N > P->Ncap || d->ncells > P->cells_cap)
+        return FCM_EINVAL;
+    P->N = d->N;
+    P->L = d->L;
+    P->a = d->a;
+    P->eta = d->eta;
+    P->sigma = d->sigma;
+    P->sigmaD = d->sigmaD;
+    P->Sigma = d->Sigma;
+    P->SigmaD = d->SigmaD;
+    P->rc = d->rc;
+    P->dx = d->dx;
+    P->m = d->m;
+    P->ncells = d->ncells;
+    P->selfVF = d->selfVF;
+    P->selfOT = d->selfOT;
+    return FCM_OK;
+}
+
+void plan_free(fcm_plan_impl* P) { free_plan(P); }
+
+int64_t plan_bytes(int64_t ncap, int grid, int precision, int cellcap, int nbins) {
+    const int64_t M = grid;
+    const int64_t rs = (int64_t)real_size(precision);
+    int64_t b = 3 * M * M * M * rs + M * 2 * rs;
+    b += 6 * ncap * (int64_t)sizeof(int);
+    b += ncap * (int64_t)(grid_rec_size(precision) + sizeof(PairRec) + sizeof(double4));
+    b += (int64_t)(2 * (nbins + 1) + 2 * (cellcap + 1)) * (int64_t)sizeof(int) + 2048 * 4 + 64;
+    return b;
+}
+
+}  // namespace fcm
+
 extern "C" {
 
 int fcm_options_default(fcm_options* opt) {
@@ -219,145 +386,14 @@ int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_del
                 double r_cut, const fcm_options* opt_in) {
     if (!out) return FCM_EINVAL;
     *out = nullptr;
-    fcm_options opt;
-    fcm_options_default(&opt);
-    if (opt_in) opt = *opt_in;
-    if (N <= 0 || N > (int64_t)1 << 29) return FCM_EINVAL;
-    if (!(L > 0.0) || !isfinite(L) || !(a > 0.0) || !isfinite(a)) return FCM_EINVAL;
-    if (!(opt.eta > 0.0) || !isfinite(opt.eta)) return FCM_EINVAL;
-    if (opt.precision != FCM_FP64 && opt.precision != FCM_FP32_BULK) return FCM_EINVAL;
-    if (opt.kahan < 0 || opt.kahan > 2) return FCM_EINVAL;
-    if (!is_smooth_even(grid)) return FCM_EINVAL;
-    const double sigma = a / sqrt(kPi);
-    const double sigmaD = a / cbrt(6.0 * sqrt(kPi));
-    if (!(sigma_delta >= sigma * (1.0 - 1e-12)) || !isfinite(sigma_delta)) return FCM_EINVAL;
-    const double Sigma = sigma_delta < sigma ? sigma : sigma_delta;
-    double SigmaD = opt.sigma_D_grid > 0.0 ? opt.sigma_D_grid : Sigma;
-    if (!(SigmaD >= sigmaD * (1.0 - 1e-12)) || !isfinite(SigmaD)) return FCM_EINVAL;
-    if (SigmaD < sigmaD) SigmaD = sigmaD;
-    if (!(r_cut >= 0.0) || !isfinite(r_cut)) return FCM_EINVAL;
-    if (r_cut >= 0.5 * L) return FCM_ERANGE;
-    const double dx = L / grid;
-    int MG = opt.support;
-    if (MG == 0) {
-        const double wmax = Sigma > SigmaD ? Sigma : SigmaD;
-        MG = (int)ceil(10.0 * wmax / dx - 1e-9);
-        if (MG & 1) ++MG;
-        if (MG < 8) MG = 8;
-    }
-    if (MG < 2 || MG > kMaxSupport || MG > grid) return FCM_EINVAL;
-    // the FP64 spreading stages 64 particles with M_G-point tables in 64 KB of LDS
-    if (opt.precision == FCM_FP64 && MG > 24) return FCM_EINVAL;
-
     fcm_plan_impl* P = new (std::nothrow) fcm_plan_impl;
     if (!P) return FCM_ENOMEM;
     memset(P, 0, sizeof(*P));
-    if (hipGetDevice(&P->device) != hipSuccess) {
-        delete P;
-        return FCM_EDEVICE;
-    }
-    P->N = N;
-    P->L = L;
-    P->a = a;
-    P->eta = opt.eta;
-    P->sigma = sigma;
-    P->sigmaD = sigmaD;
-    P->Sigma = Sigma;
-    P->SigmaD = SigmaD;
-    P->rc = r_cut;
-    P->dx = dx;
-    P->M = grid;
-    P->H = grid / 2;
-    P->MG = MG;
-    P->precision = opt.precision;
-    P->kahan = opt.kahan;
-    choose_tiles(P);
-    int m = 3;
-    if (r_cut > 0.0) {
-        const double q = L / r_cut;
-        m = q > (double)kMaxCellsPerAxis ? kMaxCellsPerAxis : (int)q;
-        if (m < 3) m = 3;
-    }
-    P->m = m;
-    P->ncells = m * m * m;
-    P->radM = make_radix_plan(grid);
-    P->radH = make_radix_plan(grid / 2);
-    finish_radix_plan(P->radM, grid);
-    finish_radix_plan(P->radH, grid);
-    const int mxy = fft_maxe(P->precision, false) * 256;
-    const int mz = fft_maxe(P->precision, true) * 256;
-    if (grid > mz) {
-        delete P;
-        return FCM_EINVAL;
-    }
-    P->Wy = pow2_floor(mxy / grid);
-    if (P->Wy > 32) P->Wy = 32;
-    P->Wz = pow2_floor(mz / grid);
-    if (P->Wz > 32) P->Wz = 32;
-    P->Wx = mxy / P->H;
-    if (P->Wx > 64) P->Wx = 64;
-    if (P->Wx < 1) P->Wx = 1;
-    {
-        const double sp = Sigma * sqrt(kPi);
-        const double d = sigma * sigma - Sigma * Sigma;
-        P->selfVF = 1.0 / (6.0 * kPi * P->eta * a) - 1.0 / (6.0 * kPi * P->eta * sp) +
-                    d / (12.0 * P->eta * sp * sp * sp) -
-                    d * d / (32.0 * P->eta * pow(Sigma, 5.0) * pow(kPi, 1.5));
-        const double sd = SigmaD * sqrt(kPi);
-        P->selfOT = 1.0 / (8.0 * kPi * P->eta * a * a * a) - 1.0 / (48.0 * P->eta * sd * sd * sd);
-    }
-
-    const size_t rs = real_size(P->precision);
-    const size_t M3 = (size_t)grid * grid * grid;
-    hipError_t e = hipSuccess;
-#define FCM_ALLOC(ptr, bytes)                                   \
-    do {                                                        \
-        if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes)); \
-    } while (0)
-    FCM_ALLOC(P->grid, 3 * M3 * rs);
-    FCM_ALLOC(P->twid, (size_t)grid * 2 * rs);
-    FCM_ALLOC(P->counts, (size_t)(P->nbins + P->ncells) * sizeof(int));
-    FCM_ALLOC(P->starts, (size_t)(P->nbins + 1 + P->ncells + 1) * sizeof(int));
-    FCM_ALLOC(P->keys, (size_t)2 * N * sizeof(int));
-    FCM_ALLOC(P->ranks, (size_t)2 * N * sizeof(int));
-    FCM_ALLOC(P->perm, (size_t)2 * N * sizeof(int));
-    FCM_ALLOC(P->scan_tmp, 2048 * sizeof(int));
-    FCM_ALLOC(P->grec, (size_t)N * grid_rec_size(P->precision));
-    FCM_ALLOC(P->prec, (size_t)N * sizeof(PairRec));
-    FCM_ALLOC(P->ppos, (size_t)N * sizeof(double4));
-    FCM_ALLOC(P->flag, 16 * sizeof(int));
-#undef FCM_ALLOC
-    if (e != hipSuccess) {
+    int st = fcm::plan_derive(P, N, L, a, sigma_delta, grid, r_cut, opt_in);
+    if (st == FCM_OK) st = fcm::plan_allocate(P, N, P->ncells);
+    if (st != FCM_OK) {
         free_plan(P);
-        return map_err(e);
-    }
-    // twiddles exp(-2 pi i m / M) in extended precision, rounded once
-    {
-        const size_t n = (size_t)grid * 2;
-        void* host = malloc(n * rs);
-        if (!host) {
-            free_plan(P);
-            return FCM_ENOMEM;
-        }
-        for (int mm = 0; mm < grid; ++mm) {
-            const long double ang = -2.0L * 3.141592653589793238462643383279502884L * mm / grid;
-            const long double c = cosl(ang), s = sinl(ang);
-            if (P->precision == FCM_FP64) {
-                ((double*)host)[2 * mm] = (double)c;
-                ((double*)host)[2 * mm + 1] = (double)s;
-            } else {
-                ((float*)host)[2 * mm] = (float)c;
-                ((float*)host)[2 * mm + 1] = (float)s;
-            }
-        }
-        e = hipMemcpy(P->twid, host, n * rs, hipMemcpyHostToDevice);
-        free(host);
-        if (e == hipSuccess) e = hipMemset(P->flag, 0, 16 * sizeof(int));
-        if (e == hipSuccess) e = hipDeviceSynchronize();
-        if (e != hipSuccess) {
-            free_plan(P);
-            return map_err(e);
-        }
+        return st;
     }
     *out = P;
     return FCM_OK;

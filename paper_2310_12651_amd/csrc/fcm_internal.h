@@ -107,6 +107,8 @@ struct PairArgs {
 struct fcm_plan_impl {
     int device;
     int64_t N;
+    int64_t Ncap;          // particles the buffers hold
+    int cells_cap;         // pair cells the buffers hold
     double L, a, eta;
     double sigma, sigmaD, Sigma, SigmaD;
     double rc, dx;
@@ -168,5 +170,14 @@ hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st,
                         hipEvent_t* ev = nullptr);
 hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool torque,
                        hipStream_t st);
+
+// plan construction pieces (fcm_api.hip), shared with the request server
+int fft_maxe(int precision, bool zpass);
+int plan_derive(fcm_plan_impl* P, int64_t N, double L, double a, double sigma_delta, int grid,
+                double r_cut, const fcm_options* opt);
+int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap);
+int plan_rebind(fcm_plan_impl* P, const fcm_plan_impl* derived);
+void plan_free(fcm_plan_impl* P);
+int64_t plan_bytes(int64_t ncap, int grid, int precision, int cellcap, int nbins);
 
 }  // namespace fcm

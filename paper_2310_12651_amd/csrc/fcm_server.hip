@@ -1,0 +1,407 @@
+// Request server for fast-FCM mobility evaluations (include/fcm_server.h).
+//
+// A worker thread owns the device work: it admits queued requests in arrival
+// order whenever one of its stream slots is free and the plan the request needs
+// fits the device-byte budget, launches the request's evaluation on that
+// slot's stream (each fcm_mobility call is stream-ordered and allocation-free),
+// records a completion event, and retires the slot when the event has fired.
+// Plans are cached and re-bound to later requests with the same grid, support
+// and precision, so grids, twiddles and sort/cell buffers stay resident;
+// idle plans are freed least-recently-used first when room is needed.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include <string.h>
+
+#include "../../include/fcm_server.h"
+#include "fcm_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct CachedPlan {
+    fcm_plan_impl* P = nullptr;
+    int64_t bytes = 0;
+    bool busy = false;
+    uint64_t last_use = 0;
+};
+
+struct Req {
+    fcm_request r;
+    int64_t ticket = 0;
+    int state = 0;   // 0 queued, 1 running, 2 done
+    int status = FCM_OK;
+    Clock::time_point t_submit, t_launch, t_done;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    Req* req = nullptr;
+    CachedPlan* plan = nullptr;
+};
+
+}  // namespace
+
+struct fcm_server_impl {
+    fcm_server_options opt;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable work_cv;   // wakes the worker
+    std::condition_variable done_cv;   // wakes waiters
+    std::deque<Req*> queue;
+    std::unordered_map<int64_t, Req*> reqs;
+    std::vector<Slot> slots;
+    std::vector<CachedPlan*> cache;
+    int64_t next_ticket = 1;
+    int64_t budget = 0;
+    uint64_t use_clock = 0;
+    bool stopping = false;
+    int inflight = 0;
+    fcm_server_stats stats;
+    std::thread worker;
+
+    void run();
+    bool retire_locked();
+    bool admit_locked();
+    CachedPlan* plan_for_locked(const fcm_plan_impl& d, int* status);
+    void evict_one_locked();
+};
+
+namespace {
+
+int64_t round_up_pow2(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+// derive the plan scalars of a request (validation included)
+int derive_request(const fcm_server_options& o, const fcm_request& r, fcm_plan_impl* d) {
+    fcm_options opt;
+    fcm_options_default(&opt);
+    opt.eta = r.eta > 0.0 ? r.eta : 1.0;
+    opt.support = r.support;
+    opt.precision = o.precision;
+    opt.kahan = o.kahan;
+    memset(d, 0, sizeof(*d));
+    return fcm::plan_derive(d, r.N, r.L, r.a, r.sigma_delta, r.grid, r.r_cut, &opt);
+}
+
+}  // namespace
+
+void fcm_server_impl::evict_one_locked() {
+    CachedPlan* victim = nullptr;
+    size_t vi = 0;
+    for (size_t i = 0; i < cache.size(); ++i) {
+        CachedPlan* c = cache[i];
+        if (!c->busy && (!victim || c->last_use < victim->last_use)) {
+            victim = c;
+            vi = i;
+        }
+    }
+    if (!victim) return;
+    cache.erase(cache.begin() + vi);
+    stats.bytes_in_use -= victim->bytes;
+    stats.plans_evicted++;
+    fcm::plan_free(victim->P);
+    delete victim;
+}
+
+CachedPlan* fcm_server_impl::plan_for_locked(const fcm_plan_impl& d, int* status) {
+    *status = FCM_OK;
+    CachedPlan* best = nullptr;
+    for (CachedPlan* c : cache) {
+        const fcm_plan_impl* P = c->P;
+        if (c->busy || P->M != d.M || P->MG != d.MG || P->precision != d.precision ||
+            P->kahan != d.kahan || P->Ncap < d.N || P->cells_cap < d.ncells)
+            continue;
+        if (!best || P->Ncap < best->P->Ncap) best = c;
+    }
+    if (best) {
+        *status = fcm::plan_rebind(best->P, &d);
+        if (*status != FCM_OK) return nullptr;
+        stats.plans_rebound++;
+        return best;
+    }
+    const int64_t ncap = round_up_pow2(d.N);
+    const int cellcap = (int)std::min<int64_t>(round_up_pow2(d.ncells), (int64_t)fcm::kMaxCellsPerAxis *
+                                                                            fcm::kMaxCellsPerAxis *
+                                                                            fcm::kMaxCellsPerAxis);
+    const int64_t bytes = fcm::plan_bytes(ncap, d.M, d.precision, cellcap, d.nbins);
+    if (bytes > budget) {
+        *status = FCM_ENOMEM;
+        return nullptr;
+    }
+    while (stats.bytes_in_use + bytes > budget) {
+        const size_t before = cache.size();
+        evict_one_locked();
+        if (cache.size() == before) return nullptr;   // everything busy: wait for a slot
+    }
+    fcm_plan_impl* P = new (std::nothrow) fcm_plan_impl;
+    if (!P) {
+        *status = FCM_ENOMEM;
+        return nullptr;
+    }
+    *P = d;
+    P->grid = nullptr;   // plan_allocate fills every buffer pointer
+    int st = fcm::plan_allocate(P, ncap, cellcap);
+    if (st != FCM_OK) {
+        fcm::plan_free(P);
+        // device memory may be held by running requests: retry after they retire
+        if (st == FCM_ENOMEM && inflight > 0) return nullptr;
+        *status = st;
+        return nullptr;
+    }
+    CachedPlan* c = new CachedPlan;
+    c->P = P;
+    c->bytes = bytes;
+    cache.push_back(c);
+    stats.plans_built++;
+    stats.bytes_in_use += bytes;
+    if (stats.bytes_in_use > stats.bytes_peak) stats.bytes_peak = stats.bytes_in_use;
+    return c;
+}
+
+// retire every slot whose completion event has fired; true if any did
+bool fcm_server_impl::retire_locked() {
+    bool any = false;
+    for (Slot& s : slots) {
+        if (!s.req) continue;
+        hipError_t q = hipEventQuery(s.done);
+        if (q == hipErrorNotReady) continue;
+        Req* r = s.req;
+        r->t_done = Clock::now();
+        if (q != hipSuccess) r->status = FCM_EDEVICE;
+        r->state = 2;
+        if (r->status == FCM_OK)
+            stats.completed++;
+        else
+            stats.failed++;
+        s.plan->busy = false;
+        s.plan->last_use = ++use_clock;
+        s.req = nullptr;
+        s.plan = nullptr;
+        --inflight;
+        any = true;
+    }
+    if (any) done_cv.notify_all();
+    return any;
+}
+
+// launch queued requests (in arrival order) while slots and memory allow
+bool fcm_server_impl::admit_locked() {
+    bool any = false;
+    while (!queue.empty()) {
+        Slot* free_slot = nullptr;
+        for (Slot& s : slots)
+            if (!s.req) {
+                free_slot = &s;
+                break;
+            }
+        if (!free_slot) break;
+        Req* r = queue.front();
+        fcm_plan_impl d;
+        int st = derive_request(opt, r->r, &d);
+        CachedPlan* c = nullptr;
+        if (st == FCM_OK) c = plan_for_locked(d, &st);
+        if (!c && st == FCM_OK) break;   // needs room held by running requests
+        queue.pop_front();
+        if (!c) {
+            r->status = st;
+            r->state = 2;
+            r->t_launch = r->t_done = Clock::now();
+            stats.failed++;
+            done_cv.notify_all();
+            any = true;
+            continue;
+        }
+        c->busy = true;
+        r->state = 1;
+        r->t_launch = Clock::now();
+        st = fcm_mobility(c->P, r->r.pos, r->r.F, r->r.T, r->r.V, r->r.Omega, free_slot->stream);
+        if (st == FCM_OK && hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess) st = FCM_EDEVICE;
+        if (st != FCM_OK) {
+            c->busy = false;
+            r->status = st;
+            r->state = 2;
+            r->t_done = Clock::now();
+            stats.failed++;
+            done_cv.notify_all();
+        } else {
+            free_slot->req = r;
+            free_slot->plan = c;
+            ++inflight;
+            if (inflight > stats.inflight_peak) stats.inflight_peak = inflight;
+        }
+        any = true;
+    }
+    return any;
+}
+
+void fcm_server_impl::run() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        bool progress = retire_locked();
+        progress = admit_locked() || progress;
+        if (stopping && queue.empty() && inflight == 0) break;
+        if (progress) continue;
+        if (inflight > 0)
+            work_cv.wait_for(lk, std::chrono::microseconds(20));
+        else
+            work_cv.wait(lk, [&] { return stopping || !queue.empty(); });
+    }
+}
+
+extern "C" {
+
+int fcm_server_options_default(fcm_server_options* o) {
+    if (!o) return FCM_EINVAL;
+    o->max_bytes = 0;
+    o->slots = 8;
+    o->precision = FCM_FP32_BULK;
+    o->kahan = 1;
+    o->max_queue = 4096;
+    return FCM_OK;
+}
+
+int fcm_server_create(fcm_server_t* out, const fcm_server_options* opt_in) {
+    if (!out) return FCM_EINVAL;
+    *out = nullptr;
+    fcm_server_options o;
+    fcm_server_options_default(&o);
+    if (opt_in) o = *opt_in;
+    if (o.slots < 1 || o.slots > 64 || o.max_queue < 1 || o.max_bytes < 0) return FCM_EINVAL;
+    if (o.precision != FCM_FP64 && o.precision != FCM_FP32_BULK) return FCM_EINVAL;
+    if (o.kahan < 0 || o.kahan > 2) return FCM_EINVAL;
+    fcm_server_impl* s = new (std::nothrow) fcm_server_impl;
+    if (!s) return FCM_ENOMEM;
+    s->opt = o;
+    memset(&s->stats, 0, sizeof(s->stats));
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return FCM_EDEVICE;
+    }
+    s->budget = o.max_bytes;
+    if (s->budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            delete s;
+            return FCM_EDEVICE;
+        }
+        s->budget = (int64_t)(0.8 * (double)fr);
+    }
+    s->slots.resize(o.slots);
+    for (Slot& sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            for (Slot& x : s->slots) {
+                if (x.stream) (void)hipStreamDestroy(x.stream);
+                if (x.done) (void)hipEventDestroy(x.done);
+            }
+            delete s;
+            return FCM_EDEVICE;
+        }
+    }
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return FCM_OK;
+}
+
+int fcm_server_submit(fcm_server_t s, const fcm_request* req, int64_t* ticket) {
+    if (!s || !req || !ticket || !req->pos || !req->F || !req->V) return FCM_EINVAL;
+    fcm_plan_impl d;
+    const int st = derive_request(s->opt, *req, &d);
+    if (st != FCM_OK) return st;
+    Req* r = new (std::nothrow) Req;
+    if (!r) return FCM_ENOMEM;
+    r->r = *req;
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stopping) {
+            delete r;
+            return FCM_EINVAL;
+        }
+        if ((int)s->queue.size() >= s->opt.max_queue) {
+            delete r;
+            return FCM_EBUSY;
+        }
+        r->ticket = s->next_ticket++;
+        s->reqs[r->ticket] = r;
+        s->queue.push_back(r);
+        s->stats.submitted++;
+        *ticket = r->ticket;
+    }
+    s->work_cv.notify_one();
+    return FCM_OK;
+}
+
+int fcm_server_poll(fcm_server_t s, int64_t ticket, int* state) {
+    if (!s || !state) return FCM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return FCM_EINVAL;
+    *state = it->second->state;
+    return it->second->state == 2 ? it->second->status : FCM_OK;
+}
+
+int fcm_server_wait(fcm_server_t s, int64_t ticket, double* queue_ms, double* run_ms) {
+    if (!s) return FCM_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return FCM_EINVAL;
+    Req* r = it->second;
+    s->work_cv.notify_one();
+    s->done_cv.wait(lk, [&] { return r->state == 2; });
+    if (queue_ms) *queue_ms = ms_between(r->t_submit, r->t_launch);
+    if (run_ms) *run_ms = ms_between(r->t_launch, r->t_done);
+    const int st = r->status;
+    s->reqs.erase(it);
+    delete r;
+    return st;
+}
+
+int fcm_server_get_stats(fcm_server_t s, fcm_server_stats* out) {
+    if (!s || !out) return FCM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    return FCM_OK;
+}
+
+int fcm_server_destroy(fcm_server_t s) {
+    if (!s) return FCM_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->work_cv.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    for (Slot& sl : s->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    for (CachedPlan* c : s->cache) {
+        fcm::plan_free(c->P);
+        delete c;
+    }
+    for (auto& kv : s->reqs) delete kv.second;
+    delete s;
+    return FCM_OK;
+}
+
+}  // extern "C"
