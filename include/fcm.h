@@ -66,8 +66,9 @@ typedef struct {
     double sigma_D_grid; /* Sigma_D, width of the torque kernel on the grid (Sec. 3.4);
                             0 = Sigma, the paper's choice                                */
     int precision;       /* FCM_FP64 or FCM_FP32_BULK (default)                          */
-    int kahan;           /* FP32 spreading sums: 0 plain FP32, 1 Kahan-compensated
-                            (default), 2 FP64 accumulators                               */
+    int kahan;           /* FP32 spreading sums: 0 plain FP32 (default: a grid point
+                            receives a few tens of terms at most), 1 Kahan-compensated,
+                            2 FP64 accumulators                                          */
 } fcm_options;
 
 /* Fill `opt` with the defaults listed above. */

@@ -53,7 +53,7 @@ typedef struct {
     int64_t max_bytes;   /* device bytes for plans; 0 = 80 % of free memory  */
     int slots;           /* requests in flight at once (default 8, <= 64)    */
     int precision;       /* FCM_FP64 or FCM_FP32_BULK (default)              */
-    int kahan;           /* as fcm_options.kahan (default 1)                 */
+    int kahan;           /* as fcm_options.kahan (default 0)                 */
     int max_queue;       /* pending requests accepted (default 4096)         */
 } fcm_server_options;
 

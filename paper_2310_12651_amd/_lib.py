@@ -134,7 +134,7 @@ class Plan:
     modified kernel width Sigma, grid^3 points, pair cut-off r_cut."""
 
     def __init__(self, N, L, a, Sigma, grid, r_cut, eta=1.0, support=0, sigma_D_grid=0.0,
-                 precision=FCM_FP32_BULK, kahan=True):
+                 precision=FCM_FP32_BULK, kahan=0):
         import torch
         lib = library()
         if isinstance(precision, str):

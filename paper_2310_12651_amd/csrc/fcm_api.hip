@@ -357,7 +357,7 @@ int fcm_options_default(fcm_options* opt) {
     opt->support = 0;
     opt->sigma_D_grid = 0.0;
     opt->precision = FCM_FP32_BULK;
-    opt->kahan = 1;
+    opt->kahan = 0;
     return FCM_OK;
 }
 

@@ -29,10 +29,10 @@ constexpr int kChunk = 32;
 
 template <typename R>
 struct alignas(16) ZTab {
-    R g;    // Gaussian of width Sigma (unnormalised)
-    R d;    // displacement
-    R d2;   // displacement squared
-    R gD;   // Gaussian of width Sigma_D
+    R g;    // Gaussian of width Sigma along z (unnormalised)
+    R gd2;  // g * dz^2
+    R gD;   // Gaussian of width Sigma_D along z
+    R gDd;  // gD * dz
 };
 
 // 2^x for x <= 0: the hardware exponential (results below the FP32 normal
@@ -91,18 +91,27 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
 
     Acc<MODE, R> acc[3][TZ];
 
+    // The bins that can reach the tile are bx in btx-backx .. btx (mod nbx)
+    // for each (by, bz) row; bins are numbered x fastest and particles are
+    // sorted by bin, so each row is one contiguous run of particles (two when
+    // it wraps around the periodic x boundary).
     for (int oz = 0; oz <= a.backz; ++oz) {
         int bz = btz - oz;
         if (bz < 0) bz += a.nbz;
         for (int oy = 0; oy <= a.backy; ++oy) {
             int by = bty - oy;
             if (by < 0) by += a.nby;
-            for (int ox = 0; ox <= a.backx; ++ox) {
-                int bx = btx - ox;
-                if (bx < 0) bx += a.nbx;
-                const int b = bx + a.nbx * (by + a.nby * bz);
-                const int beg = bin_start[b], end = bin_start[b + 1];
+            const int row = a.nbx * (by + a.nby * bz);
+            const int bx0 = btx - a.backx;
+            const bool wraps = bx0 < 0;
+            const int beg0 = bin_start[row + (wraps ? bx0 + a.nbx : bx0)];
+            const int end0 = bin_start[row + (wraps ? a.nbx : btx + 1)];
+            const int beg1 = wraps ? bin_start[row] : 0;
+            const int end1 = wraps ? bin_start[row + btx + 1] : 0;
+            for (int run = 0; run < 2; ++run) {
+                const int beg = run ? beg1 : beg0, end = run ? end1 : end0;
                 for (int base = beg; base < end; base += kChunk) {
+                    // 1. stage the contributors of this chunk
                     const int p = base + lane;
                     bool take = false;
                     GridRec<R> r;
@@ -119,21 +128,22 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                     }
                     const unsigned long long mask = __ballot(take);
                     const int cnt = __popcll(mask);
-                    if (take) {
-                        const int slot = __popcll(mask & ((1ull << lane) - 1ull));
-                        stg[slot] = r;
-                        for (int t = 0; t < MG; ++t) {
-                            const R d = ((R)t - r.f[2]) * dx;
-                            const R d2 = d * d;
-                            ZTab<R> e;
-                            e.g = fexp2(-d2 * a.e2);
-                            e.d = d;
-                            e.d2 = d2;
-                            e.gD = SAMEW ? e.g : fexp2(-d2 * a.e2D);
-                            zt[slot * MG + t] = e;
-                        }
+                    if (take) stg[__popcll(mask & ((1ull << lane) - 1ull))] = r;
+                    __syncthreads();
+                    // 2. their z factors, one table entry per lane
+                    for (int e = lane; e < cnt * MG; e += 64) {
+                        const int s = (e * a.mgmul) >> 16, t = e - s * MG;
+                        const R d = ((R)t - stg[s].f[2]) * dx;
+                        const R d2 = d * d;
+                        ZTab<R> z;
+                        z.g = fexp2(-d2 * a.e2);
+                        z.gd2 = z.g * d2;
+                        z.gD = SAMEW ? z.g : fexp2(-d2 * a.e2D);
+                        z.gDd = z.gD * d;
+                        zt[e] = z;
                     }
                     __syncthreads();
+                    // 3. accumulate
                     for (int q = 0; q < cnt; ++q) {
                         const int sx = __builtin_amdgcn_readfirstlane(stg[q].s[0]);
                         const int sy = __builtin_amdgcn_readfirstlane(stg[q].s[1]);
@@ -147,40 +157,84 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                         const R dyv = ((R)dyi - stg[q].f[1]) * dx;
                         const R x2 = dxv * dxv, y2 = dyv * dyv;
                         const R gxy = in ? fexp2(-(x2 + y2) * a.e2) : (R)0;
-                        const R base_w = gxy * (a.A + a.B * (x2 + y2));
-                        const R gB = gxy * a.B;
-                        const R F0 = stg[q].F[0], F1 = stg[q].F[1], F2 = stg[q].F[2];
-                        R gxyD = gxy, T0 = 0, T1 = 0, ax = 0, ay = 0, az = 0;
-                        if (TORQUE) {
-                            if (!SAMEW) gxyD = in ? fexp2(-(x2 + y2) * a.e2D) : (R)0;
-                            T0 = stg[q].T[0];
-                            T1 = stg[q].T[1];
-                            const R T2 = stg[q].T[2];
-                            ax = -T2 * dyv;
-                            ay = T2 * dxv;
-                            az = T0 * dyv - T1 * dxv;
+                        // Column coefficients: with g_z, d_z the z factors, the
+                        // contribution to component c at height z is
+                        //   g_z (P_c + d_z^2 Q_c) + gD_z (Pt_c + d_z S_c)
+                        // where P, Q carry the force kernel g_xy (A + B r_xy^2 +
+                        // B d_z^2) F_c and Pt, S the torque kernel's T x d split
+                        // into its d_z-free part and its d_z coefficient.
+                        const R wf = gxy * (a.A + a.B * (x2 + y2));
+                        const R wq = gxy * a.B;
+                        R P[3], Q[3], Pt[3] = {0, 0, 0}, S0 = 0, S1 = 0;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            P[c] = wf * stg[q].F[c];
+                            Q[c] = wq * stg[q].F[c];
                         }
+                        if (TORQUE) {
+                            const R gxyD = SAMEW ? gxy : (in ? fexp2(-(x2 + y2) * a.e2D) : (R)0);
+                            const R T0 = stg[q].T[0], T1 = stg[q].T[1], T2 = stg[q].T[2];
+                            // T x d = (T1 dz - T2 dy, T2 dx - T0 dz, T0 dy - T1 dx)
+                            Pt[0] = -gxyD * T2 * dyv;
+                            Pt[1] = gxyD * T2 * dxv;
+                            Pt[2] = gxyD * (T0 * dyv - T1 * dxv);
+                            S0 = gxyD * T1;
+                            S1 = -gxyD * T0;
+                            if (SAMEW) {
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) P[c] += Pt[c];
+                            }
+                        }
+                        // tile heights k with (Z0 + k - sz) mod M < MG: one or
+                        // two runs, as a bit mask
                         int dz0 = Z0 - sz;
                         if (dz0 < 0) dz0 += M;
+                        const int hi1 = min(TZ, MG - dz0);
+                        const int lo2 = M - dz0;
+                        const int hi2 = min(TZ, M - dz0 + MG);
+                        unsigned kmask = hi1 > 0 ? (1u << hi1) - 1u : 0u;
+                        if (lo2 < TZ) kmask |= ((1u << hi2) - 1u) & ~((1u << lo2) - 1u);
+                        kmask = __builtin_amdgcn_readfirstlane(kmask);
                         const ZTab<R>* zq = zt + q * MG;
 #pragma unroll
                         for (int k = 0; k < TZ; ++k) {
-                            int dzi = dz0 + k;
-                            if (dzi >= M) dzi -= M;
-                            if (dzi < MG) {
+                            if (kmask & (1u << k)) {
+                                int dzi = dz0 + k;
+                                if (dzi >= M) dzi -= M;
                                 const ZTab<R> e = zq[dzi];
-                                const R w = e.g * (base_w + gB * e.d2);
-                                if (TORQUE) {
-                                    const R wt = e.gD * gxyD;
-                                    const R tx = ax + T1 * e.d;
-                                    const R ty = ay - T0 * e.d;
-                                    acc[0][k].add(w * F0 + wt * tx);
-                                    acc[1][k].add(w * F1 + wt * ty);
-                                    acc[2][k].add(w * F2 + wt * az);
+                                if (MODE == ACC_PLAIN) {
+                                    R v0 = acc[0][k].s, v1 = acc[1][k].s, v2 = acc[2][k].s;
+                                    v0 = v0 + e.g * P[0] + e.gd2 * Q[0];
+                                    v1 = v1 + e.g * P[1] + e.gd2 * Q[1];
+                                    v2 = v2 + e.g * P[2] + e.gd2 * Q[2];
+                                    if (TORQUE) {
+                                        if (!SAMEW) {
+                                            v0 = v0 + e.gD * Pt[0];
+                                            v1 = v1 + e.gD * Pt[1];
+                                            v2 = v2 + e.gD * Pt[2];
+                                        }
+                                        v0 = v0 + e.gDd * S0;
+                                        v1 = v1 + e.gDd * S1;
+                                    }
+                                    acc[0][k].s = v0;
+                                    acc[1][k].s = v1;
+                                    acc[2][k].s = v2;
                                 } else {
-                                    acc[0][k].add(w * F0);
-                                    acc[1][k].add(w * F1);
-                                    acc[2][k].add(w * F2);
+                                    R v0 = e.g * P[0] + e.gd2 * Q[0];
+                                    R v1 = e.g * P[1] + e.gd2 * Q[1];
+                                    R v2 = e.g * P[2] + e.gd2 * Q[2];
+                                    if (TORQUE) {
+                                        if (!SAMEW) {
+                                            v0 = v0 + e.gD * Pt[0];
+                                            v1 = v1 + e.gD * Pt[1];
+                                            v2 = v2 + e.gD * Pt[2];
+                                        }
+                                        v0 = v0 + e.gDd * S0;
+                                        v1 = v1 + e.gDd * S1;
+                                    }
+                                    acc[0][k].add(v0);
+                                    acc[1][k].add(v1);
+                                    acc[2][k].add(v2);
                                 }
                             }
                         }
@@ -223,11 +277,12 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
     const R dx = a.dx;
     if (lane < MG) {
         const R d = ((R)lane - r.f[2]) * dx;
+        const R d2 = d * d;
         ZTab<R> e;
-        e.d = d;
-        e.d2 = d * d;
-        e.g = fexp2(-e.d2 * a.e2);
-        e.gD = SAMEW ? e.g : fexp2(-e.d2 * a.e2D);
+        e.g = fexp2(-d2 * a.e2);
+        e.gd2 = e.g * d2;
+        e.gD = SAMEW ? e.g : fexp2(-d2 * a.e2D);
+        e.gDd = e.gD * d;
         zt[wave][lane] = e;
     }
     __syncthreads();
@@ -258,15 +313,13 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
             A0[0] += e.g * u0;
             A0[1] += e.g * u1;
             A0[2] += e.g * u2;
-            const R gd2 = e.g * e.d2;
-            A2[0] += gd2 * u0;
-            A2[1] += gd2 * u1;
-            A2[2] += gd2 * u2;
+            A2[0] += e.gd2 * u0;
+            A2[1] += e.gd2 * u1;
+            A2[2] += e.gd2 * u2;
             if (OMEGA) {
-                const R gdd = e.gD * e.d;
-                D1[0] += gdd * u0;
-                D1[1] += gdd * u1;
-                D1[2] += gdd * u2;
+                D1[0] += e.gDd * u0;
+                D1[1] += e.gDd * u1;
+                D1[2] += e.gDd * u2;
                 if (!SAMEW) {
                     D0[0] += e.gD * u0;
                     D0[1] += e.gD * u1;
@@ -328,7 +381,7 @@ GridArgs<R> make_args(const fcm_plan_impl* P) {
     a.backx = P->backx;
     a.backy = P->backy;
     a.backz = P->backz;
-    a.remap8 = (P->nbins % 8 == 0) ? 1 : 0;
+    a.mgmul = 65536 / P->MG + 1;
     a.dx = (R)P->dx;
     const double log2e = 1.4426950408889634074;
     a.e2 = (R)(log2e / (2.0 * P->Sigma * P->Sigma));

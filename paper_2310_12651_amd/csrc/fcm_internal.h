@@ -85,7 +85,7 @@ struct GridArgs {
     int TX, TY, TZ;                // spread tile (points)
     int nbx, nby, nbz;             // tiles (= bins) per axis
     int backx, backy, backz;       // bins scanned before the tile's own
-    int remap8;                    // 1 = spread XCD-aware tile remap
+    int mgmul;                     // 65536 / MG + 1: e / MG = (e * mgmul) >> 16 for e < 1024
     R dx;                          // grid spacing
     R e2;                          // log2(e) / (2 Sigma^2)
     R e2D;                         // log2(e) / (2 Sigma_D^2)

@@ -273,7 +273,7 @@ int fcm_server_options_default(fcm_server_options* o) {
     o->max_bytes = 0;
     o->slots = 8;
     o->precision = FCM_FP32_BULK;
-    o->kahan = 1;
+    o->kahan = 0;
     o->max_queue = 4096;
     return FCM_OK;
 }

@@ -69,7 +69,7 @@ def _check(st, where):
 class Server:
     """Continuous-batching request server on the current device."""
 
-    def __init__(self, slots=8, precision=FCM_FP32_BULK, kahan=1, max_bytes=0, max_queue=4096):
+    def __init__(self, slots=8, precision=FCM_FP32_BULK, kahan=0, max_bytes=0, max_queue=4096):
         lib = _lib()
         o = ServerOptions()
         _check(lib.fcm_server_options_default(ctypes.byref(o)), "fcm_server_options_default")

@@ -45,7 +45,7 @@ def test_status_strings_and_defaults(lib):
     assert fcm.status_string(0) == "ok"
     assert "cut-off" in fcm.status_string(fcm.FCM_ERANGE)
     o = fcm.fcm_options_default()
-    assert o.eta == 1.0 and o.support == 0 and o.precision == fcm.FCM_FP32_BULK and o.kahan == 1
+    assert o.eta == 1.0 and o.support == 0 and o.precision == fcm.FCM_FP32_BULK and o.kahan == 0
 
 
 def _plan(lib, N=10, L=20.0, a=1.0, Sigma=1.0, grid=32, rc=5.0, **kw):
