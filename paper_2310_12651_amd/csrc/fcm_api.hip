@@ -148,8 +148,9 @@ hipEvent_t* call_events(fcm_plan_impl* P) {
 void free_plan(fcm_plan_impl* P) {
     if (!P) return;
     free_events(P);
-    void* bufs[] = {P->grid, P->twid, P->counts, P->starts, P->keys, P->ranks,
-                    P->perm, P->scan_tmp, P->grec, P->prec, P->ppos, P->flag};
+    void* bufs[] = {P->grid,  P->twid, P->counts, P->starts,    P->keys,       P->ranks,
+                    P->perm,  P->scan_tmp, P->grec, P->prec,    P->ppos,       P->flag,
+                    P->pair_hits, P->pair_count};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete P;
@@ -161,14 +162,18 @@ int map_err(hipError_t e) {
     return FCM_EDEVICE;
 }
 
+// Counting sort into grid bins and pair cells.  The counts are all zero
+// between calls (the scan clears them); after an allocation or a failed launch
+// they are cleared here first.
 hipError_t sort_particles(fcm_plan_impl* P, const double* pos, hipStream_t st) {
     hipError_t e;
-    if ((e = launch_fill(P->counts, P->nbins + P->ncells, 0, st)) != hipSuccess) return e;
-    if ((e = launch_hash(P, pos, st)) != hipSuccess) return e;
-    if ((e = launch_scan(P->counts, P->starts, P->nbins, P->scan_tmp, st)) != hipSuccess) return e;
-    if ((e = launch_scan(P->counts + P->nbins, P->starts + P->nbins + 1, P->ncells, P->scan_tmp,
-                         st)) != hipSuccess)
+    if (P->counts_dirty &&
+        (e = launch_fill(P->counts, P->nbins + P->cells_cap, 0, st)) != hipSuccess)
         return e;
+    P->counts_dirty = 1;
+    if ((e = launch_hash(P, pos, st)) != hipSuccess) return e;
+    if ((e = launch_scan(P, st)) != hipSuccess) return e;
+    P->counts_dirty = 0;
     return launch_scatter(P, st);
 }
 
@@ -183,6 +188,7 @@ namespace fcm {
 // Validate the arguments and fill every scalar of a plan (no allocation).
 int plan_derive(fcm_plan_impl* P, int64_t N, double L, double a, double sigma_delta, int grid,
                 double r_cut, const fcm_options* opt_in) {
+    memset(P, 0, sizeof(*P));  // no buffers, no events, no stream yet
     fcm_options opt;
     fcm_options_default(&opt);
     if (opt_in) opt = *opt_in;
@@ -269,6 +275,7 @@ int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
     if (hipGetDevice(&P->device) != hipSuccess) return FCM_EDEVICE;
     P->Ncap = ncap;
     P->cells_cap = cellcap;
+    P->counts_dirty = 1;
     const int grid = P->M;
     const size_t rs = real_size(P->precision);
     const size_t M3 = (size_t)grid * grid * grid;
@@ -288,6 +295,8 @@ int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
     FCM_ALLOC(P->grec, (size_t)ncap * grid_rec_size(P->precision));
     FCM_ALLOC(P->prec, (size_t)ncap * sizeof(PairRec));
     FCM_ALLOC(P->ppos, (size_t)ncap * sizeof(double4));
+    FCM_ALLOC(P->pair_hits, (size_t)3 * ncap * kPairCap * sizeof(int));
+    FCM_ALLOC(P->pair_count, (size_t)3 * ncap * sizeof(int));
     FCM_ALLOC(P->flag, 16 * sizeof(int));
 #undef FCM_ALLOC
     if (e != hipSuccess) return map_err(e);
@@ -342,6 +351,7 @@ int64_t plan_bytes(int64_t ncap, int grid, int precision, int cellcap, int nbins
     const int64_t rs = (int64_t)real_size(precision);
     int64_t b = 3 * M * M * M * rs + M * 2 * rs;
     b += 6 * ncap * (int64_t)sizeof(int);
+    b += 3 * ncap * (int64_t)(kPairCap + 1) * (int64_t)sizeof(int);
     b += ncap * (int64_t)(grid_rec_size(precision) + sizeof(PairRec) + sizeof(double4));
     b += (int64_t)(2 * (nbins + 1) + 2 * (cellcap + 1)) * (int64_t)sizeof(int) + 2048 * 4 + 64;
     return b;
@@ -429,17 +439,16 @@ int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double*
         if (ev) (void)hipEventRecord(ev[i], st);
     };
     mark(0);
+    const bool corr = needs_correction(p);
     hipError_t e = sort_particles(p, pos, st);
-    if (e == hipSuccess) e = launch_gather_grid(p, pos, F, T, st);
+    if (e == hipSuccess)
+        e = corr ? launch_gather_both(p, pos, F, T, st) : launch_gather_grid(p, pos, F, T, st);
     mark(1);
     if (e == hipSuccess) e = launch_spread(p, T != nullptr, p->grid, st);
     if (e == hipSuccess) e = launch_solve(p, p->grid, st, ev ? ev + 2 : nullptr);
     if (e == hipSuccess) e = launch_interp(p, p->grid, V, Omega, st);
     mark(8);
-    if (e == hipSuccess && needs_correction(p)) {
-        e = launch_gather_pair(p, pos, F, T, st);
-        if (e == hipSuccess) e = launch_pair(p, V, Omega, T != nullptr, st);
-    }
+    if (e == hipSuccess && corr) e = launch_pair(p, V, Omega, T != nullptr, st);
     mark(9);
     return map_err(e);
 }

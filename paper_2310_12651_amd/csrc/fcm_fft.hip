@@ -17,6 +17,8 @@
 // y[(j div Ns) Ns R + k + r Ns].  Every thread holds its butterflies of a
 // stage in registers between a barrier-separated read and write, so a tile
 // is transformed in place.
+#include <utility>
+
 #include "fcm_internal.h"
 
 namespace fcm {
@@ -357,6 +359,247 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__
     }
 }
 
+// ---- register-resident transforms for M = N1 N2 (FP32) ----
+//
+// A length-M transform of W adjacent columns is done by W N2 threads: thread
+// (w, p) holds the N1 elements x[j1 N2 + p] of column w, transforms them in
+// registers (an N1-point DFT), multiplies by exp(+-2 pi i p k1 / M), and one
+// LDS exchange hands thread (w, k1) the N2 values of index k1; an N2-point DFT
+// in registers then gives X[k1 + N1 k2] (four-step Cooley-Tukey).  The inverse
+// used after the projection runs the same steps in the opposite order, from
+// that spectral layout back to x[a + N2 b] in thread (w, a).  Each element
+// crosses LDS once per transform instead of once per radix stage.
+
+// cos and sin of 2 pi m / n at compile time: exact quadrant reduction, then
+// Taylor series on [0, pi/2)
+constexpr double ct_sin_q(double x) {
+    double t = x, s = x;
+    for (int i = 1; i < 16; ++i) {
+        t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+        s += t;
+    }
+    return s;
+}
+constexpr double ct_cos_q(double x) {
+    double t = 1.0, s = 1.0;
+    for (int i = 1; i < 16; ++i) {
+        t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+        s += t;
+    }
+    return s;
+}
+constexpr double ct_cos(long m, long n) {
+    m %= n;
+    if (m < 0) m += n;
+    const long q = (4 * m) / n, r = 4 * m - q * n;
+    const double x = 1.57079632679489661923 * (double)r / (double)n;
+    return q == 0 ? ct_cos_q(x) : q == 1 ? -ct_sin_q(x) : q == 2 ? -ct_cos_q(x) : ct_sin_q(x);
+}
+constexpr double ct_sin(long m, long n) {
+    m %= n;
+    if (m < 0) m += n;
+    const long q = (4 * m) / n, r = 4 * m - q * n;
+    const double x = 1.57079632679489661923 * (double)r / (double)n;
+    return q == 0 ? ct_sin_q(x) : q == 1 ? ct_cos_q(x) : q == 2 ? -ct_sin_q(x) : -ct_cos_q(x);
+}
+
+// v * exp(DIR 2 pi i K / N), K and N compile-time
+template <typename R, int N, int DIR, int K>
+__device__ inline C2<R> twc(C2<R> v) {
+    if constexpr (K % N == 0) {
+        return v;
+    } else {
+        constexpr double c = ct_cos(K, N), sn = DIR * ct_sin(K, N);
+        return C2<R>{v.x * (R)c - v.y * (R)sn, v.x * (R)sn + v.y * (R)c};
+    }
+}
+
+template <int... I, typename F>
+__device__ inline void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ inline void static_for(F&& f) {
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+// in-register DFT of length N (natural order in and out)
+template <typename R, int N, int DIR>
+struct RDFT {
+    static constexpr int P = (N % 4 == 0) ? 4 : ((N % 2 == 0) ? 2 : 3);
+    static constexpr int S = N / P;
+    static __device__ inline void run(C2<R>* x) {
+        C2<R> e[P][S];
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+#pragma unroll
+            for (int m = 0; m < S; ++m) e[r][m] = x[P * m + r];
+#pragma unroll
+        for (int r = 0; r < P; ++r) RDFT<R, S, DIR>::run(e[r]);
+        static_for<S>([&](auto k) {
+            C2<R> t[P];
+            static_for<P>([&](auto r) {
+                constexpr int rk = decltype(r)::value * decltype(k)::value;
+                t[decltype(r)::value] = twc<R, N, DIR, rk>(e[decltype(r)::value][decltype(k)::value]);
+            });
+            DFT<R, P, DIR>::run(t);
+#pragma unroll
+            for (int q = 0; q < P; ++q) x[decltype(k)::value + S * q] = t[q];
+        });
+    }
+};
+template <typename R, int DIR>
+struct RDFT<R, 1, DIR> {
+    static __device__ inline void run(C2<R>*) {}
+};
+template <typename R, int DIR>
+struct RDFT<R, 2, DIR> {
+    static __device__ inline void run(C2<R>* x) { DFT<R, 2, DIR>::run(x); }
+};
+template <typename R, int DIR>
+struct RDFT<R, 3, DIR> {
+    static __device__ inline void run(C2<R>* x) { DFT<R, 3, DIR>::run(x); }
+};
+template <typename R, int DIR>
+struct RDFT<R, 4, DIR> {
+    static __device__ inline void run(C2<R>* x) { DFT<R, 4, DIR>::run(x); }
+};
+template <typename R, int DIR>
+struct RDFT<R, 8, DIR> {
+    static __device__ inline void run(C2<R>* x) { DFT<R, 8, DIR>::run(x); }
+};
+
+template <int N1, int N2, int W>
+struct RegGeom {
+    static_assert(N1 == N2, "square split only");
+    static constexpr int M = N1 * N2;
+    static constexpr int H = M / 2;
+    static constexpr int NT = W * N2;        // threads per block
+    static constexpr int PL = N2 * W + 8;    // exchange-buffer plane stride (complex)
+    static constexpr int NG = H / W;         // column groups per row of kx
+    static_assert(H % W == 0, "W must divide M/2");
+};
+
+// thread (w, p): v[j1] = x[j1 N2 + p]  ->  v[k2] = X[p + N1 k2]
+template <int N1, int N2, int W, int DIR>
+__device__ inline void reg_fft_fwd(C2<float>* v, const C2<float>* tw, C2<float>* E, int w, int p) {
+    using G = RegGeom<N1, N2, W>;
+    RDFT<float, N1, DIR>::run(v);
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+        C2<float> t = tw[p * k1];
+        if (DIR > 0) t.y = -t.y;
+        v[k1] = cmul(v[k1], t);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) E[k1 * G::PL + p * W + w] = v[k1];
+    __syncthreads();
+#pragma unroll
+    for (int j2 = 0; j2 < N2; ++j2) v[j2] = E[p * G::PL + j2 * W + w];
+    __syncthreads();
+    RDFT<float, N2, DIR>::run(v);
+}
+
+// thread (w, p): v[k2] = X[p + N1 k2]  ->  v[b] = x[p + N2 b] (inverse, unnormalised)
+template <int N1, int N2, int W>
+__device__ inline void reg_fft_inv_spec(C2<float>* v, const C2<float>* tw, C2<float>* E, int w,
+                                        int p) {
+    using G = RegGeom<N1, N2, W>;
+    RDFT<float, N2, 1>::run(v);
+#pragma unroll
+    for (int a = 1; a < N2; ++a) {
+        C2<float> t = tw[p * a];
+        t.y = -t.y;
+        v[a] = cmul(v[a], t);
+    }
+#pragma unroll
+    for (int a = 0; a < N2; ++a) E[a * G::PL + p * W + w] = v[a];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = E[p * G::PL + k1 * W + w];
+    __syncthreads();
+    RDFT<float, N1, 1>::run(v);
+}
+
+// y pass (register form): one (component, z) plane and W kx columns per block
+template <int N1, int N2, int W, int DIR>
+__global__ __launch_bounds__(W * N2) void k_fft_y_reg(
+    C2<float>* __restrict__ spec, const C2<float>* __restrict__ twg) {
+    using G = RegGeom<N1, N2, W>;
+    __shared__ C2<float> tw[G::M];
+    __shared__ C2<float> E[N1 * G::PL];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = blk % G::NG, plane = blk / G::NG;
+    const int w = threadIdx.x % W, p = threadIdx.x / W;
+    char* base = (char*)(spec + (size_t)plane * G::M * G::H + g * W);
+    const unsigned lo = ((unsigned)p * G::H + (unsigned)w) * 8u;
+    auto at = [&](unsigned off) -> C2<float>& { return *(C2<float>*)(base + off); };
+    for (int e = threadIdx.x; e < G::M; e += G::NT) tw[e] = twg[e];
+    C2<float> v[N1];
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) v[j1] = at(lo + j1 * N2 * G::H * 8u);
+    __syncthreads();
+    reg_fft_fwd<N1, N2, W, DIR>(v, tw, E, w, p);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) at(lo + N1 * k2 * G::H * 8u) = v[k2];
+}
+
+// z pass (register form): forward FFT along z of the three components of W kx
+// columns at one ky, the projection, and the inverse FFT along z
+template <int N1, int N2, int W>
+__global__ __launch_bounds__(W * N2) void k_fft_z_solve_reg(
+    C2<float>* __restrict__ spec, const C2<float>* __restrict__ twg, ProjArgs pa) {
+    using G = RegGeom<N1, N2, W>;
+    constexpr int M = G::M, H = G::H;
+    __shared__ C2<float> tw[M];
+    __shared__ C2<float> E[N1 * G::PL];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = blk % G::NG, y = blk / G::NG;
+    const int w = threadIdx.x % W, p = threadIdx.x / W;
+    // byte offsets from a block-uniform base: 3 M^2 H 8 bytes < 2^32 for M <= 512
+    static_assert((unsigned long long)3 * M * M * H * 8 < (1ull << 32), "offsets exceed 32 bits");
+    constexpr unsigned cstride = (unsigned)M * M * H * 8u, zstride = (unsigned)M * H * 8u;
+    char* base = (char*)(spec + (size_t)y * H + g * W);
+    const unsigned lo = (unsigned)p * zstride + (unsigned)w * 8u;
+    auto at = [&](unsigned off) -> C2<float>& { return *(C2<float>*)(base + off); };
+    for (int e = threadIdx.x; e < M; e += G::NT) tw[e] = twg[e];
+    C2<float> v[3][N1];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j1 = 0; j1 < N1; ++j1) v[c][j1] = at(lo + (c * cstride + j1 * N2 * zstride));
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) reg_fft_fwd<N1, N2, W, -1>(v[c], tw, E, w, p);
+    // projection: u^ = (I - k k^T / k^2) f^ / (eta k^2 M^3); k = 0 and index-H modes -> 0
+    const float ku = (float)pa.kunit, sc = (float)pa.scale;
+    const int jx = g * W + w;
+    const int jy = y < H ? y : y - M;
+    const float kx = ku * (float)jx, ky = ku * (float)jy;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+        const int iz = p + N1 * k2;
+        const int jz = iz < H ? iz : iz - M;
+        const bool zero = (y == H) || (iz == H) || (jx == 0 && jy == 0 && jz == 0);
+        const float kz = ku * (float)jz;
+        const float k2s = kx * kx + ky * ky + kz * kz;
+        const float ik2 = zero ? 0.0f : 1.0f / k2s;
+        const C2<float> f0 = v[0][k2], f1 = v[1][k2], f2 = v[2][k2];
+        const C2<float> kf = {(kx * f0.x + ky * f1.x + kz * f2.x) * ik2,
+                              (kx * f0.y + ky * f1.y + kz * f2.y) * ik2};
+        const float s = sc * ik2;
+        v[0][k2] = C2<float>{(f0.x - kx * kf.x) * s, (f0.y - kx * kf.y) * s};
+        v[1][k2] = C2<float>{(f1.x - ky * kf.x) * s, (f1.y - ky * kf.y) * s};
+        v[2][k2] = C2<float>{(f2.x - kz * kf.x) * s, (f2.y - kz * kf.y) * s};
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) reg_fft_inv_spec<N1, N2, W>(v[c], tw, E, w, p);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < N1; ++b) at(lo + (c * cstride + N2 * b * zstride)) = v[c][b];
+}
+
 template <typename R, int MX, int MZ>
 hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* ev) {
     auto mark = [&](int i) {
@@ -380,19 +623,37 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
     const int ngy = (H + P->Wy - 1) / P->Wy;
     const size_t shy = (M + (size_t)P->Wy * M) * cs;
     const int lwy = __builtin_ctz(P->Wy), lwz = __builtin_ctz(P->Wz);
-    hipLaunchKernelGGL((k_fft_y<R, -1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec,
-                       tw, M, P->radM, P->Wy, lwy);
-    mark(2);
-    {
-        const int ngz = (H + P->Wz - 1) / P->Wz;
-        const size_t shz = (M + 3 * (size_t)P->Wz * M) * cs;
-        hipLaunchKernelGGL((k_fft_z_solve<R, MZ>), dim3(ngz * M), dim3(kFFTThreads), shz, st, spec,
-                           tw, M, P->radM, P->Wz, lwz, pa);
+    if constexpr (sizeof(R) == sizeof(float)) {
+        if (M == 256) {
+            using G = RegGeom<16, 16, 16>;
+            C2<float>* sp = (C2<float>*)spec;
+            const C2<float>* tf = (const C2<float>*)tw;
+            hipLaunchKernelGGL((k_fft_y_reg<16, 16, 16, -1>), dim3(G::NG * 3 * M), dim3(G::NT), 0, st,
+                               sp, tf);
+            mark(2);
+            hipLaunchKernelGGL((k_fft_z_solve_reg<16, 16, 16>), dim3(G::NG * M), dim3(G::NT), 0, st, sp,
+                               tf, pa);
+            mark(3);
+            hipLaunchKernelGGL((k_fft_y_reg<16, 16, 16, 1>), dim3(G::NG * 3 * M), dim3(G::NT), 0, st,
+                               sp, tf);
+            mark(4);
+        }
     }
-    mark(3);
-    hipLaunchKernelGGL((k_fft_y<R, 1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec, tw,
-                       M, P->radM, P->Wy, lwy);
-    mark(4);
+    if (sizeof(R) != sizeof(float) || M != 256) {
+        hipLaunchKernelGGL((k_fft_y<R, -1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec,
+                           tw, M, P->radM, P->Wy, lwy);
+        mark(2);
+        {
+            const int ngz = (H + P->Wz - 1) / P->Wz;
+            const size_t shz = (M + 3 * (size_t)P->Wz * M) * cs;
+            hipLaunchKernelGGL((k_fft_z_solve<R, MZ>), dim3(ngz * M), dim3(kFFTThreads), shz, st,
+                               spec, tw, M, P->radM, P->Wz, lwz, pa);
+        }
+        mark(3);
+        hipLaunchKernelGGL((k_fft_y<R, 1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec,
+                           tw, M, P->radM, P->Wy, lwy);
+        mark(4);
+    }
     {
         const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;
         hipLaunchKernelGGL((k_fft_x_c2r<R, MX>), dim3((nlines + P->Wx - 1) / P->Wx),

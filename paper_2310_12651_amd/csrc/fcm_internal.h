@@ -14,6 +14,7 @@ constexpr int kMaxRadixStages = 16;
 constexpr int kMaxSupport = 32;      // largest M_G accepted
 constexpr int kMaxGrid = 1024;       // largest grid per axis accepted
 constexpr int kMaxCellsPerAxis = 128;
+constexpr int kPairCap = 16;         // neighbours recorded per (particle, z layer)
 
 template <typename R>
 struct C2 {
@@ -136,9 +137,11 @@ struct fcm_plan_impl {
     void* grec;            // N GridRec
     fcm::PairRec* prec;    // N PairRec
     double4* ppos;         // N wrapped positions in pair order (w unused)
+    int* pair_hits;        // 3N x kPairCap neighbours found by the pair scan
+    int* pair_count;       // 3N neighbour counts
     int* flag;             // [0] = non-finite position seen
     hipStream_t last_stream;
-    int sorted_valid;
+    int counts_dirty;      // counts may be non-zero (cleared by the next sort)
     // per-stage timing
     int timing;
     int ev_calls;           // calls recorded
@@ -152,14 +155,18 @@ namespace fcm {
 hipError_t launch_fill(int* p, int n, int v, hipStream_t st);
 // wrap + hash (Sec. 4, spatial hashing) for the grid bins and the pair cells
 hipError_t launch_hash(const fcm_plan_impl* P, const double* pos, hipStream_t st);
-// exclusive scan of counts[0..n) into starts[0..n], starts[n] = total
-hipError_t launch_scan(const int* counts, int* starts, int n, int* tmp, hipStream_t st);
+// exclusive scans of the bin and cell counts into starts (each with its total
+// appended); clears the counts
+hipError_t launch_scan(const fcm_plan_impl* P, hipStream_t st);
 // counting-sort scatter and in-segment ordering by original index
 hipError_t launch_scatter(const fcm_plan_impl* P, hipStream_t st);
 // gather the sorted per-particle records
 hipError_t launch_gather_grid(const fcm_plan_impl* P, const double* pos, const double* F,
                               const double* T, hipStream_t st);
 hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const double* F,
+                              const double* T, hipStream_t st);
+// both of the above in one launch (F required)
+hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const double* F,
                               const double* T, hipStream_t st);
 
 hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st);

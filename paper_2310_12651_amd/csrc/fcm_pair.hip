@@ -2,12 +2,22 @@
 // Sec. 3.2 eq. correction_VF; Sec. 3.4 eqs. correction_WF, correction_WT) and
 // the self corrections of App. B.
 //
-// One thread per particle, in pair-cell order: it scans its own and the 26
-// adjacent cells (cells are at least R_c wide, Sec. 4 spatial hashing),
-// takes the minimum image of every candidate and, for r < R_c, adds
-//   V_n     += C_VF(x) F_m + C_VT(x) T_m,   Omega_n += C_OF(x) F_m + C_OT(x) T_m
-// with x = Y_n - Y_m.  Each ordered pair is evaluated by its own receiving
-// particle, so no atomics are needed and the result is deterministic.
+// Particles are in pair-cell order.  For every particle n and every neighbour
+// m with r = |x| < R_c (x = Y_n - Y_m, minimum image; cells are at least R_c
+// wide, Sec. 4 spatial hashing) the receiving particle gets
+//   V_n     += C_VF(x) F_m + C_VT(x) T_m,   Omega_n += C_OF(x) F_m + C_OT(x) T_m.
+// Each ordered pair is evaluated for its receiving particle, so no atomics are
+// needed, and every sum is taken in a fixed order: the result is deterministic.
+//
+// Work split, two launches.  The scan runs one thread per (particle, z layer
+// of the 3x3x3 neighbour cells); cells are numbered x fastest, so the three x
+// neighbours of a cell row are one contiguous run of particles (two when the
+// row wraps).  It touches only compact positions and records up to kPairCap
+// neighbours per thread.  The evaluation takes kPairPerBlock consecutive
+// particles per workgroup, queues their recorded pairs in LDS order and
+// evaluates them with all threads, so the FP64 body (erfc, exp) runs with
+// full wavefronts; a thread whose layer had more neighbours than fit rescans
+// it and evaluates the rest itself.
 //
 // The blocks, with xh = x/r and (-x cross) T = T x x:
 //   C_VF = Avf I + Bvf xh xh^T    (S(sigma sqrt2) - S~ - (sigma^2-Sigma^2) Q(Sigma sqrt2)
@@ -83,8 +93,10 @@ __device__ inline Coef correction_coeffs(double r, const PairArgs& a) {
     return c;
 }
 
-constexpr int kPairThreads = 256;
-constexpr int kHitBuf = 16;
+constexpr int kPairPerBlock = 85;                 // evaluation: particles per workgroup
+constexpr int kPairThreads = 3 * kPairPerBlock;   // one thread per (particle, z layer)
+constexpr int kPairBlock = 256;                   // launched threads (the last one idles)
+constexpr int kScanBlock = 256;
 
 // add the corrections from one neighbour m at x = Y_n - Y_m (r^2 = r2 < R_c^2)
 __device__ inline void add_pair(double x0, double x1, double x2, double r2, const PairRec& o,
@@ -116,77 +128,208 @@ __device__ inline void add_pair(double x0, double x1, double x2, double r2, cons
     w[2] += c.fof * (F0 * x1 - F1 * x0) + c.Aot * T2 + c.Bot * h2 * hT;
 }
 
-// The candidate scan touches only the compact positions; the pairs found are
-// buffered per lane and evaluated together, so the expensive FP64 body runs
-// with the wavefront converged instead of once per candidate position.
-__global__ __launch_bounds__(kPairThreads) void k_pair(const double4* __restrict__ pos4,
-                                                       const PairRec* __restrict__ rec,
-                                                       const int* __restrict__ cell_start,
-                                                       PairArgs a, double* __restrict__ V,
-                                                       double* __restrict__ W) {
-    __shared__ int hits[kPairThreads][kHitBuf + 1];
-    const int j = xcd_remap(blockIdx.x, gridDim.x) * kPairThreads + threadIdx.x;
-    if (j >= a.N) return;
-    int* hb = hits[threadIdx.x];
-    const PairRec me = rec[j];
-    const double4 mp = pos4[j];
-    double v[3] = {a.selfVF * me.F[0], a.selfVF * me.F[1], a.selfVF * me.F[2]};
-    double w[3] = {a.selfOT * me.T[0], a.selfOT * me.T[1], a.selfOT * me.T[2]};
+__device__ inline double4 min_image(double4 p, double4 o, double L, double iL) {
+    double x0 = p.x - o.x, x1 = p.y - o.y, x2 = p.z - o.z;
+    x0 -= L * rint(x0 * iL);
+    x1 -= L * rint(x1 * iL);
+    x2 -= L * rint(x2 * iL);
+    return make_double4(x0, x1, x2, x0 * x0 + x1 * x1 + x2 * x2);
+}
+
+// Neighbours of particle j (position mp, cell `cell`) in the z layer `layer`
+// (0, 1, 2 = cz-1, cz, cz+1) within R_c, q != j: hit(q) for each, in a fixed
+// order.  Candidate positions are loaded four at a time.
+template <class Hit>
+__device__ inline void scan_layer(const double4* __restrict__ pos4, const int* __restrict__ cell_start,
+                                  const PairArgs& a, int j, double4 mp, int cell, int layer,
+                                  Hit&& hit) {
     const double L = a.L, iL = 1.0 / a.L;
-    auto flush = [&](int n) {
-        for (int h = 0; h < n; ++h) {
-            const int q = hb[h];
-            const double4 op = pos4[q];
-            double x0 = mp.x - op.x, x1 = mp.y - op.y, x2 = mp.z - op.z;
-            x0 -= L * rint(x0 * iL);
-            x1 -= L * rint(x1 * iL);
-            x2 -= L * rint(x2 * iL);
-            add_pair(x0, x1, x2, x0 * x0 + x1 * x1 + x2 * x2, rec[q], a, v, w);
+    const int m = a.m;
+    const int cx = cell % m, cy = (cell / m) % m, cz = cell / (m * m);
+    int nz = cz + layer - 1;
+    nz = nz < 0 ? nz + m : (nz >= m ? nz - m : nz);
+    // x neighbours cx-1, cx, cx+1 (mod m) of the three rows: one or two runs of cells
+    int rb[6], re[6];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        int ny = cy + r - 1;
+        ny = ny < 0 ? ny + m : (ny >= m ? ny - m : ny);
+        const int row = m * (ny + m * nz);
+        if (cx == 0) {
+            rb[2 * r] = cell_start[row + m - 1];
+            re[2 * r] = cell_start[row + m];
+            rb[2 * r + 1] = cell_start[row];
+            re[2 * r + 1] = cell_start[row + 2];
+        } else if (cx == m - 1) {
+            rb[2 * r] = cell_start[row + m - 2];
+            re[2 * r] = cell_start[row + m];
+            rb[2 * r + 1] = cell_start[row];
+            re[2 * r + 1] = cell_start[row + 1];
+        } else {
+            rb[2 * r] = cell_start[row + cx - 1];
+            re[2 * r] = cell_start[row + cx + 2];
+            rb[2 * r + 1] = 0;
+            re[2 * r + 1] = 0;
         }
-    };
-    if (a.with_pairs) {
-        const int m = a.m;
-        const int cx = me.cell % m, cy = (me.cell / m) % m, cz = me.cell / (m * m);
-        int nh = 0;
-        for (int oz = -1; oz <= 1; ++oz) {
-            int nz = cz + oz;
-            nz = nz < 0 ? nz + m : (nz >= m ? nz - m : nz);
-            for (int oy = -1; oy <= 1; ++oy) {
-                int ny = cy + oy;
-                ny = ny < 0 ? ny + m : (ny >= m ? ny - m : ny);
-                for (int ox = -1; ox <= 1; ++ox) {
-                    int nx = cx + ox;
-                    nx = nx < 0 ? nx + m : (nx >= m ? nx - m : nx);
-                    const int nc = nx + m * (ny + m * nz);
-                    const int b = cell_start[nc], e = cell_start[nc + 1];
-                    for (int q = b; q < e; ++q) {
-                        const double4 op = pos4[q];
-                        double x0 = mp.x - op.x, x1 = mp.y - op.y, x2 = mp.z - op.z;
-                        x0 -= L * rint(x0 * iL);
-                        x1 -= L * rint(x1 * iL);
-                        x2 -= L * rint(x2 * iL);
-                        const double r2 = x0 * x0 + x1 * x1 + x2 * x2;
-                        if (q != j && r2 < a.rc2) {
-                            hb[nh++] = q;
-                            if (nh == kHitBuf) {
-                                flush(nh);
-                                nh = 0;
-                            }
-                        }
-                    }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int b = rb[k], e = re[k];
+        for (int q0 = b; q0 < e; q0 += 4) {
+            double4 c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] = pos4[min(q0 + u, e - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u;
+                if (q < e) {
+                    const double4 x = min_image(mp, c[u], L, iL);
+                    if (q != j && x.w < a.rc2) hit(q);
                 }
             }
         }
-        flush(nh);
     }
-    const int64_t n = me.orig;
-    V[3 * n + 0] += v[0];
-    V[3 * n + 1] += v[1];
-    V[3 * n + 2] += v[2];
-    if (W) {
-        W[3 * n + 0] += w[0];
-        W[3 * n + 1] += w[1];
-        W[3 * n + 2] += w[2];
+}
+
+// thread t = 3 j + layer records the first kPairCap neighbours of particle j
+// in its layer and their total count
+__global__ __launch_bounds__(kScanBlock) void k_pair_scan(const double4* __restrict__ pos4,
+                                                          const PairRec* __restrict__ rec,
+                                                          const int* __restrict__ cell_start,
+                                                          PairArgs a, int* __restrict__ hits,
+                                                          int* __restrict__ count) {
+    const int t = xcd_remap(blockIdx.x, gridDim.x) * kScanBlock + threadIdx.x;
+    if (t >= 3 * a.N) return;
+    const int j = t / 3, layer = t - 3 * j;
+    int n = 0;
+    int* h = hits + (size_t)t * kPairCap;
+    scan_layer(pos4, cell_start, a, j, pos4[j], rec[j].cell, layer, [&](int q) {
+        if (n < kPairCap) h[n] = q;
+        ++n;
+    });
+    count[t] = n;
+}
+
+__global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restrict__ pos4,
+                                                          const PairRec* __restrict__ rec,
+                                                          const int* __restrict__ cell_start,
+                                                          const int* __restrict__ hits,
+                                                          const int* __restrict__ count,
+                                                          PairArgs a, double* __restrict__ V,
+                                                          double* __restrict__ W) {
+    __shared__ int qoff[kPairBlock + 1];         // queue offset of each thread's pairs
+    __shared__ int wsum[kPairBlock / 64];
+    __shared__ double res[kPairBlock][6];        // evaluated pairs of one round
+    const int tid = threadIdx.x;
+    const int base = xcd_remap(blockIdx.x, gridDim.x) * kPairPerBlock;
+    const int pl = tid / 3, layer = tid - 3 * pl;  // local particle, z layer
+    const int j = base + pl;
+    const bool active = tid < kPairThreads && j < a.N;
+    const double L = a.L, iL = 1.0 / a.L;
+    const size_t t0 = (size_t)3 * base;          // scan thread of local thread 0
+    const int ntrue = (active && a.with_pairs) ? count[t0 + tid] : 0;
+    const int nh = min(ntrue, kPairCap);
+
+    // queue offsets: exclusive scan of the per-thread counts
+    {
+        const int lane = tid & 63, wid = tid >> 6;
+        int inc = nh;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
+        }
+        if (lane == 63) wsum[wid] = inc;
+        __syncthreads();
+        int pre = 0;
+        for (int k = 0; k < wid; ++k) pre += wsum[k];
+        qoff[tid] = pre + inc - nh;
+        if (tid == kPairBlock - 1) qoff[kPairBlock] = pre + inc;
+        __syncthreads();
+    }
+    const int total = qoff[kPairBlock];
+
+    // evaluate the queue in rounds of kPairBlock pairs; the layer-0 thread of
+    // each particle adds its particle's results of the round in queue order
+    double v[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+    for (int r0 = 0; r0 < total; r0 += kPairBlock) {
+        const int e = r0 + tid;
+        if (e < total) {
+            // the thread that recorded pair e: the last one whose offset is <= e
+            int lo = 0, hi = kPairBlock - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (qoff[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            const int q = hits[(t0 + lo) * kPairCap + (e - qoff[lo])];
+            const double4 y = min_image(pos4[base + lo / 3], pos4[q], L, iL);
+            double rv[3] = {0, 0, 0}, rw[3] = {0, 0, 0};
+            add_pair(y.x, y.y, y.z, y.w, rec[q], a, rv, rw);
+            res[tid][0] = rv[0];
+            res[tid][1] = rv[1];
+            res[tid][2] = rv[2];
+            res[tid][3] = rw[0];
+            res[tid][4] = rw[1];
+            res[tid][5] = rw[2];
+        }
+        __syncthreads();
+        if (active && layer == 0) {
+            const int lo = max(qoff[tid], r0), hi = min(qoff[tid + 3], r0 + kPairBlock);
+            for (int k = lo; k < hi; ++k) {
+                const double* rr = res[k - r0];
+                v[0] += rr[0];
+                v[1] += rr[1];
+                v[2] += rr[2];
+                w[0] += rr[3];
+                w[1] += rr[4];
+                w[2] += rr[5];
+            }
+        }
+        __syncthreads();
+    }
+
+    // neighbours beyond the recorded ones: rescan and evaluate them here
+    double pv[3] = {0, 0, 0}, pw[3] = {0, 0, 0};
+    if (ntrue > kPairCap) {
+        const double4 mp = pos4[j];
+        int k = 0;
+        scan_layer(pos4, cell_start, a, j, mp, rec[j].cell, layer, [&](int q) {
+            if (k++ >= kPairCap) {
+                const double4 y = min_image(mp, pos4[q], L, iL);
+                add_pair(y.x, y.y, y.z, y.w, rec[q], a, pv, pw);
+            }
+        });
+    }
+    if (active) {
+        res[tid][0] = pv[0];
+        res[tid][1] = pv[1];
+        res[tid][2] = pv[2];
+        res[tid][3] = pw[0];
+        res[tid][4] = pw[1];
+        res[tid][5] = pw[2];
+    }
+    __syncthreads();
+    if (active && layer == 0) {
+        const PairRec me = rec[j];
+#pragma unroll
+        for (int l = 0; l <= 2; ++l) {
+            v[0] += res[tid + l][0];
+            v[1] += res[tid + l][1];
+            v[2] += res[tid + l][2];
+            w[0] += res[tid + l][3];
+            w[1] += res[tid + l][4];
+            w[2] += res[tid + l][5];
+        }
+        const int64_t n = me.orig;
+        V[3 * n + 0] += a.selfVF * me.F[0] + v[0];
+        V[3 * n + 1] += a.selfVF * me.F[1] + v[1];
+        V[3 * n + 2] += a.selfVF * me.F[2] + v[2];
+        if (W) {
+            W[3 * n + 0] += a.selfOT * me.T[0] + w[0];
+            W[3 * n + 1] += a.selfOT * me.T[1] + w[1];
+            W[3 * n + 2] += a.selfOT * me.T[2] + w[2];
+        }
     }
 }
 
@@ -208,8 +351,12 @@ hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torq
     a.selfVF = P->selfVF;
     a.selfOT = P->selfOT;
     a.with_pairs = P->rc > 0.0 ? 1 : 0;
-    hipLaunchKernelGGL(k_pair, dim3((a.N + kPairThreads - 1) / kPairThreads), dim3(kPairThreads), 0,
-                       st, P->ppos, P->prec, P->starts + P->nbins + 1, a, V, W);
+    const int* cs = P->starts + P->nbins + 1;
+    if (a.with_pairs)
+        hipLaunchKernelGGL(k_pair_scan, dim3((3 * a.N + kScanBlock - 1) / kScanBlock), dim3(kScanBlock),
+                           0, st, P->ppos, P->prec, cs, a, P->pair_hits, P->pair_count);
+    hipLaunchKernelGGL(k_pair_eval, dim3((a.N + kPairPerBlock - 1) / kPairPerBlock), dim3(kPairBlock),
+                       0, st, P->ppos, P->prec, cs, P->pair_hits, P->pair_count, a, V, W);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanPerThread = 16;
 constexpr int kScanTile = kScanThreads * kScanPerThread;   // 4096
-constexpr int kScanTopThreads = 1024;
+constexpr int kMaxScanTiles = 2048;              // scan_tmp entries
 
 struct HashArgs {
     int N, M, MG;
@@ -107,46 +107,77 @@ __device__ inline int block_inclusive_scan(int v, int* sh) {
     return v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* __restrict__ in, int n,
-                                                               int* __restrict__ sums) {
+// Exclusive scans of two count arrays in two launches.  The arrays A (grid
+// bins, nA entries) and B (pair cells, nB entries) are cut into tiles of
+// kScanTile; block b < tA handles tile b of A, the others tile b - tA of B.
+__device__ inline void scan2_tile(int b, int nA, int nB, int tA, int* n, int* base, int* first) {
+    if (b < tA) {
+        *n = nA;
+        *base = b * kScanTile;
+        *first = 0;
+    } else {
+        *n = nB;
+        *base = (b - tA) * kScanTile;
+        *first = tA;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan2_reduce(const int* __restrict__ counts,
+                                                                int nA, int nB, int tA,
+                                                                int* __restrict__ sums) {
     __shared__ int sh[kScanThreads / 64];
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    int n, base, first;
+    scan2_tile(blockIdx.x, nA, nB, tA, &n, &base, &first);
+    const int* in = blockIdx.x < tA ? counts : counts + nA;
+    const int i0 = base + threadIdx.x * kScanPerThread;
     int v = 0;
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k)
-        if (base + k < n) v += in[base + k];
+        if (i0 + k < n) v += in[i0 + k];
     v = block_inclusive_scan<kScanThreads>(v, sh);
     if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = v;
 }
 
-__global__ __launch_bounds__(kScanTopThreads) void k_scan_top(int* __restrict__ sums, int nb) {
-    __shared__ int sh[kScanTopThreads / 64];
-    int v = threadIdx.x < nb ? sums[threadIdx.x] : 0;
-    int inc = block_inclusive_scan<kScanTopThreads>(v, sh);
-    if (threadIdx.x < nb) sums[threadIdx.x] = inc - v;     // exclusive
-    if (threadIdx.x == kScanTopThreads - 1) sums[nb] = inc;  // total
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int* __restrict__ in, int n,
-                                                             const int* __restrict__ sums,
-                                                             int* __restrict__ out, int nb) {
+// Writes out[0..n] (out[n] = total) for each array and clears the counts it
+// read, so the next hash starts from zero.
+__global__ __launch_bounds__(kScanThreads) void k_scan2_down(int* __restrict__ counts, int nA,
+                                                              int nB, int tA, int tB,
+                                                              const int* __restrict__ sums,
+                                                              int* __restrict__ outA,
+                                                              int* __restrict__ outB) {
     __shared__ int sh[kScanThreads / 64];
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    int n, base, first;
+    scan2_tile(blockIdx.x, nA, nB, tA, &n, &base, &first);
+    int* in = blockIdx.x < tA ? counts : counts + nA;
+    int* out = blockIdx.x < tA ? outA : outB;
+    const int last = blockIdx.x < tA ? tA - 1 : tA + tB - 1;
+    // sum of the tiles before this one in its array
+    __shared__ int tile_pre;
+    int pre = 0;
+    for (int t = first + threadIdx.x; t < (int)blockIdx.x; t += kScanThreads) pre += sums[t];
+    pre = block_inclusive_scan<kScanThreads>(pre, sh);
+    if (threadIdx.x == kScanThreads - 1) tile_pre = pre;
+    __syncthreads();
+    pre = tile_pre;
+    const int i0 = base + threadIdx.x * kScanPerThread;
     int loc[kScanPerThread];
     int v = 0;
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
-        loc[k] = (base + k < n) ? in[base + k] : 0;
+        loc[k] = (i0 + k < n) ? in[i0 + k] : 0;
         v += loc[k];
     }
-    int inc = block_inclusive_scan<kScanThreads>(v, sh);
-    int run = sums[blockIdx.x] + inc - v;
+    const int inc = block_inclusive_scan<kScanThreads>(v, sh);
+    int run = pre + inc - v;
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
-        if (base + k < n) out[base + k] = run;
+        if (i0 + k < n) {
+            out[i0 + k] = run;
+            in[i0 + k] = 0;
+        }
         run += loc[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
+    if ((int)blockIdx.x == last && threadIdx.x == kScanThreads - 1) out[n] = run;
 }
 
 __global__ void k_scatter(const int* __restrict__ keys, const int* __restrict__ ranks,
@@ -158,19 +189,28 @@ __global__ void k_scatter(const int* __restrict__ keys, const int* __restrict__ 
     perm[N + start_cell[keys[N + i]] + ranks[N + i]] = i;
 }
 
-// order each segment [start[s], start[s+1]) of perm by value (insertion sort)
-__global__ void k_segment_order(const int* __restrict__ start, int nseg, int* __restrict__ perm) {
+// order each segment of perm by value (insertion sort): segments 0..nbins-1
+// are the grid bins (perm[0..N)), the next ncells the pair cells (perm[N..2N))
+__global__ void k_segment_order(const int* __restrict__ starts, int nbins, int ncells, int N,
+                                int* __restrict__ perm) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nseg) return;
-    int b = start[s], e = start[s + 1];
+    if (s >= nbins + ncells) return;
+    const int* start = starts;
+    int* pm = perm;
+    if (s >= nbins) {
+        s -= nbins;
+        start = starts + nbins + 1;
+        pm = perm + N;
+    }
+    const int b = start[s], e = start[s + 1];
     for (int i = b + 1; i < e; ++i) {
-        int v = perm[i];
+        const int v = pm[i];
         int j = i - 1;
-        while (j >= b && perm[j] > v) {
-            perm[j + 1] = perm[j];
+        while (j >= b && pm[j] > v) {
+            pm[j + 1] = pm[j];
             --j;
         }
-        perm[j + 1] = v;
+        pm[j + 1] = v;
     }
 }
 
@@ -219,6 +259,48 @@ __global__ void k_gather_pair(const double* __restrict__ pos, const double* __re
     pos4[j] = make_double4(r.y[0], r.y[1], r.y[2], 0.0);
 }
 
+// both gathers in one launch: threads [0, N) build the grid records, threads
+// [N, 2N) the pair records
+template <typename R>
+__global__ void k_gather_both(const double* __restrict__ pos, const double* __restrict__ F,
+                              const double* __restrict__ T, const int* __restrict__ perm, int N,
+                              int M, int MG, double L, double dx, double normF, double normT,
+                              GridRec<R>* __restrict__ grec, const int* __restrict__ cellkey,
+                              PairRec* __restrict__ prec, double4* __restrict__ pos4) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * N) return;
+    int bad = 0;
+    if (t < N) {
+        const int i = perm[t];
+        GridRec<R> r;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double w = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
+            const int su = support_start(w, dx, MG);
+            r.s[a] = wrap_index(su, M);
+            r.f[a] = (R)(w / dx - (double)su);
+            r.F[a] = (R)(F[3 * (int64_t)i + a] * normF);
+            r.T[a] = T ? (R)(T[3 * (int64_t)i + a] * normT) : (R)0;
+        }
+        r.orig = i;
+        grec[t] = r;
+    } else {
+        const int j = t - N;
+        const int i = perm[N + j];
+        PairRec r;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r.y[a] = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
+            r.F[a] = F[3 * (int64_t)i + a];
+            r.T[a] = T ? T[3 * (int64_t)i + a] : 0.0;
+        }
+        r.orig = i;
+        r.cell = cellkey[i];
+        prec[j] = r;
+        pos4[j] = make_double4(r.y[0], r.y[1], r.y[2], 0.0);
+    }
+}
+
 inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -250,12 +332,14 @@ hipError_t launch_hash(const fcm_plan_impl* P, const double* pos, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const int* counts, int* starts, int n, int* tmp, hipStream_t st) {
-    int nb = blocks_for(n, kScanTile);
-    if (nb > kScanTopThreads) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, counts, n, tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopThreads), 0, st, tmp, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, counts, n, tmp, starts, nb);
+hipError_t launch_scan(const fcm_plan_impl* P, hipStream_t st) {
+    const int nA = P->nbins, nB = P->ncells;
+    const int tA = blocks_for(nA, kScanTile), tB = blocks_for(nB, kScanTile);
+    if (tA + tB > kMaxScanTiles) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan2_reduce, dim3(tA + tB), dim3(kScanThreads), 0, st, P->counts, nA, nB,
+                       tA, P->scan_tmp);
+    hipLaunchKernelGGL(k_scan2_down, dim3(tA + tB), dim3(kScanThreads), 0, st, P->counts, nA, nB,
+                       tA, tB, P->scan_tmp, P->starts, P->starts + nA + 1);
     return hipGetLastError();
 }
 
@@ -265,10 +349,8 @@ hipError_t launch_scatter(const fcm_plan_impl* P, hipStream_t st) {
     const int* sc = P->starts + P->nbins + 1;
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(N, 256)), dim3(256), 0, st, P->keys, P->ranks, sb,
                        sc, P->perm, N);
-    hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(P->nbins, 256)), dim3(256), 0, st, sb,
-                       P->nbins, P->perm);
-    hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(P->ncells, 256)), dim3(256), 0, st, sc,
-                       P->ncells, P->perm + N);
+    hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(P->nbins + P->ncells, 256)), dim3(256), 0,
+                       st, P->starts, P->nbins, P->ncells, N, P->perm);
     return hipGetLastError();
 }
 
@@ -294,6 +376,29 @@ hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const d
     int N = (int)P->N;
     hipLaunchKernelGGL(k_gather_pair, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, F, T,
                        P->perm + N, P->keys + N, N, P->L, P->prec, P->ppos);
+    return hipGetLastError();
+}
+
+}  // namespace fcm
+
+namespace fcm {
+
+hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const double* F,
+                              const double* T, hipStream_t st) {
+    const int N = (int)P->N;
+    const double pi = 3.14159265358979323846;
+    const double normF = pow(2.0 * pi * P->Sigma * P->Sigma, -1.5);
+    const double normT =
+        pow(2.0 * pi * P->SigmaD * P->SigmaD, -1.5) / (2.0 * P->SigmaD * P->SigmaD);
+    const dim3 g(blocks_for(2 * (int64_t)N, 256)), b(256);
+    if (P->precision == FCM_FP64)
+        hipLaunchKernelGGL(k_gather_both<double>, g, b, 0, st, pos, F, T, P->perm, N, P->M, P->MG,
+                           P->L, P->dx, normF, normT, (GridRec<double>*)P->grec, P->keys + N,
+                           P->prec, P->ppos);
+    else
+        hipLaunchKernelGGL(k_gather_both<float>, g, b, 0, st, pos, F, T, P->perm, N, P->M, P->MG,
+                           P->L, P->dx, normF, normT, (GridRec<float>*)P->grec, P->keys + N,
+                           P->prec, P->ppos);
     return hipGetLastError();
 }
 

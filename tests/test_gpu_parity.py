@@ -5,7 +5,8 @@ FP32-bulk plans within 1e-5 normwise relative.  Each operator of the path is
 checked on its own (spread, Stokes solve, interpolation, correction) and the
 whole mobility end to end, on grids that span several tiles and ragged
 tilings (grid sizes with factors of 3, odd supports), wrapped positions,
-torques on and off, a separate torque width, standard FCM, and N = 1.
+torques on and off, a separate torque width, standard FCM, a crowded box
+(R_c near L/2, many neighbours per particle), and N = 1.
 """
 
 import math
@@ -48,6 +49,14 @@ def _case(name):
         w = dict(N=N, L=L, a=A, eta=1.0, grid=48, Sigma=SIG, M_G=14, R_c=0.0,
                  Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
         return w, None
+    if name == "crowded":
+        # R_c near L/2: ~130 neighbours per particle, more than the pair scan
+        # records per (particle, z layer), so the evaluation's rescan path runs
+        L, N = 30.0, 300
+        Y = workloads.rsa_positions(N, L, A, rng)
+        w = dict(N=N, L=L, a=A, eta=1.0, grid=36, Sigma=1.2, M_G=12, R_c=14.0,
+                 Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+        return w, None
     if name == "single":
         w = dict(N=1, L=16.0, a=A, eta=1.0, grid=24, Sigma=2 * SIG, M_G=12, R_c=7.5,
                  Y=np.array([[15.9, 0.01, 8.0]]), F=np.array([[1.0, -2.0, 0.5]]),
@@ -56,7 +65,7 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["small", "ragged54", "wideTorque36", "standard48", "single"]
+CASES = ["small", "ragged54", "wideTorque36", "standard48", "crowded", "single"]
 PREC = {"fp64": (0, 1e-10), "fp32": (1, 1e-5)}
 
 
