@@ -469,6 +469,17 @@ struct RDFT<R, 8, DIR> {
     static __device__ inline void run(C2<R>* x) { DFT<R, 8, DIR>::run(x); }
 };
 
+// raw buffer access (word 3 of the resource: 32-bit data format, as for all
+// gfx9-family raw buffers)
+constexpr int kBufferWord3 = 0x00020000;
+__device__ inline C2<float> buf_load(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    return __builtin_bit_cast(C2<float>, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+__device__ inline void buf_store(C2<float> v, __amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), rs, voff, soff, 0);
+}
+
 template <int N1, int N2, int W>
 struct RegGeom {
     static_assert(N1 == N2, "square split only");
@@ -556,18 +567,20 @@ __global__ __launch_bounds__(W * N2) void k_fft_z_solve_reg(
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int g = blk % G::NG, y = blk / G::NG;
     const int w = threadIdx.x % W, p = threadIdx.x / W;
-    // byte offsets from a block-uniform base: 3 M^2 H 8 bytes < 2^32 for M <= 512
-    static_assert((unsigned long long)3 * M * M * H * 8 < (1ull << 32), "offsets exceed 32 bits");
-    constexpr unsigned cstride = (unsigned)M * M * H * 8u, zstride = (unsigned)M * H * 8u;
-    char* base = (char*)(spec + (size_t)y * H + g * W);
-    const unsigned lo = (unsigned)p * zstride + (unsigned)w * 8u;
-    auto at = [&](unsigned off) -> C2<float>& { return *(C2<float>*)(base + off); };
+    // Buffer loads and stores: one 32-bit lane offset plus a scalar offset per
+    // element, instead of a 64-bit address per element held in registers.
+    static_assert((unsigned long long)3 * M * M * H * 8 < (1ull << 31), "offsets exceed 31 bits");
+    constexpr int cstride = M * M * H * 8, zstride = M * H * 8;
+    C2<float>* base = spec + (size_t)y * H + g * W;
+    const int nbytes = (int)(((size_t)3 * M * M * H - ((size_t)y * H + g * W)) * 8);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nbytes, kBufferWord3);
+    const int lo = p * zstride + w * 8;
     for (int e = threadIdx.x; e < M; e += G::NT) tw[e] = twg[e];
     C2<float> v[3][N1];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int j1 = 0; j1 < N1; ++j1) v[c][j1] = at(lo + (c * cstride + j1 * N2 * zstride));
+        for (int j1 = 0; j1 < N1; ++j1) v[c][j1] = buf_load(rs, lo, c * cstride + j1 * N2 * zstride);
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c) reg_fft_fwd<N1, N2, W, -1>(v[c], tw, E, w, p);
@@ -597,7 +610,127 @@ __global__ __launch_bounds__(W * N2) void k_fft_z_solve_reg(
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int b = 0; b < N1; ++b) at(lo + (c * cstride + N2 * b * zstride)) = v[c][b];
+        for (int b = 0; b < N1; ++b) buf_store(v[c][b], rs, lo, c * cstride + N2 * b * zstride);
+}
+
+// x passes (register form) for a half-length H = N1 N2 with N1 = 2 N2:
+// T = N2 threads per line, each holding the N1 complex values of index
+// congruent to its lane q modulo T.  Step 1 is an N1-point DFT per thread,
+// step 2 two N2-point DFTs per thread after one LDS exchange; the result
+// X[q + T i] lands back in the same lane-modulo-T layout, so the real/complex
+// split, which pairs index k with H - k, only needs lane shuffles: the
+// partner of (q, i) is lane T - q, register N1 - 1 - i (lane 0: itself,
+// register (N1 - i) mod N1).
+template <int N1, int N2>
+struct XGeom {
+    static_assert(N1 == 2 * N2, "N1 = 2 N2");
+    static constexpr int H = N1 * N2, M = 2 * H, T = N2;
+    static constexpr int NT = 256, LPB = NT / T;   // threads, lines per block
+    static constexpr int KS = N2 + 1;              // exchange: k1 stride (complex)
+    static constexpr int LS = 168;                 // exchange: line stride (complex)
+    static_assert(N1 * KS <= LS, "line stride");
+};
+
+template <int N1, int N2, int DIR>
+__device__ inline void xfft_two_step(C2<float>* v, const C2<float>* tw, C2<float>* E, int q) {
+    using G = XGeom<N1, N2>;
+    // v[j1] = z[j1 T + q]
+    RDFT<float, N1, DIR>::run(v);
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+        C2<float> t = tw[2 * q * k1];   // exp(-2 pi i q k1 / H)
+        if (DIR > 0) t.y = -t.y;
+        v[k1] = cmul(v[k1], t);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) E[k1 * G::KS + q] = v[k1];
+    __syncthreads();
+    C2<float> u[2][N2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int j2 = 0; j2 < N2; ++j2) u[s2][j2] = E[(q + G::T * s2) * G::KS + j2];
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) RDFT<float, N2, DIR>::run(u[s2]);
+    // X[k1 + N1 k2] with k1 = q + T s2  ->  X[q + T i], i = s2 + 2 k2
+#pragma unroll
+    for (int i = 0; i < N1; ++i) v[i] = u[i & 1][i >> 1];
+}
+
+__device__ inline C2<float> shfl_c(C2<float> v, int src) {
+    return C2<float>{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__(256) void k_fft_x_r2c_reg(float* __restrict__ grid,
+                                                       const C2<float>* __restrict__ twg, int nlines) {
+    using G = XGeom<N1, N2>;
+    constexpr int H = G::H, T = G::T;
+    __shared__ C2<float> tw[G::M];
+    __shared__ C2<float> E[G::LPB * G::LS];
+    const int tid = threadIdx.x, q = tid % T, ll = tid / T;
+    const int line = xcd_remap(blockIdx.x, gridDim.x) * G::LPB + ll;
+    const bool ok = line < nlines;
+    C2<float>* g = reinterpret_cast<C2<float>*>(grid) + (size_t)(ok ? line : 0) * H;
+    for (int e = tid; e < G::M; e += G::NT) tw[e] = twg[e];
+    C2<float> v[N1];
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) v[j1] = ok ? g[j1 * T + q] : C2<float>{0, 0};
+    __syncthreads();
+    xfft_two_step<N1, N2, -1>(v, tw, E + ll * G::LS, q);
+    // split: X_k = (Z_k + conj Z_{H-k})/2 - (i/2) exp(-2 pi i k/M) (Z_k - conj Z_{H-k})
+    const int lane = threadIdx.x & 63;
+    const int partner = (lane & ~(T - 1)) | ((T - q) & (T - 1));
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+        const C2<float> a = shfl_c(v[N1 - 1 - i], partner);
+        C2<float> Zc = (q == 0) ? v[(N1 - i) % N1] : a;
+        Zc.y = -Zc.y;
+        const int k = q + T * i;
+        const C2<float> S = cadd(v[i], Zc), D = csub(v[i], Zc);
+        const C2<float> WD = cmul(tw[k], D);
+        if (ok) g[k] = C2<float>{0.5f * (S.x + WD.y), 0.5f * (S.y - WD.x)};
+    }
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__(256) void k_fft_x_c2r_reg(float* __restrict__ grid,
+                                                       const C2<float>* __restrict__ twg, int nlines) {
+    using G = XGeom<N1, N2>;
+    constexpr int H = G::H, T = G::T;
+    __shared__ C2<float> tw[G::M];
+    __shared__ C2<float> E[G::LPB * G::LS];
+    const int tid = threadIdx.x, q = tid % T, ll = tid / T;
+    const int line = xcd_remap(blockIdx.x, gridDim.x) * G::LPB + ll;
+    const bool ok = line < nlines;
+    C2<float>* g = reinterpret_cast<C2<float>*>(grid) + (size_t)(ok ? line : 0) * H;
+    for (int e = tid; e < G::M; e += G::NT) tw[e] = twg[e];
+    C2<float> x[N1];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) x[i] = ok ? g[q + T * i] : C2<float>{0, 0};
+    __syncthreads();
+    // Z_k = E + i O, E = X_k + conj X_{H-k}, O = exp(+2 pi i k/M) (X_k - conj X_{H-k}),
+    // with the x-Nyquist coefficient X_H taken as 0
+    const int lane = threadIdx.x & 63;
+    const int partner = (lane & ~(T - 1)) | ((T - q) & (T - 1));
+    C2<float> z[N1];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+        const C2<float> a = shfl_c(x[N1 - 1 - i], partner);
+        C2<float> Xc = (q == 0) ? (i == 0 ? C2<float>{0, 0} : x[(N1 - i) % N1]) : a;
+        Xc.y = -Xc.y;
+        const int k = q + T * i;
+        const C2<float> Ev = cadd(x[i], Xc);
+        C2<float> wk = tw[k];
+        wk.y = -wk.y;
+        const C2<float> O = cmul(csub(x[i], Xc), wk);
+        z[i] = C2<float>{Ev.x - O.y, Ev.y + O.x};
+    }
+    xfft_two_step<N1, N2, 1>(z, tw, E + ll * G::LS, q);
+#pragma unroll
+    for (int i = 0; i < N1; ++i)
+        if (ok) g[q + T * i] = z[i];
 }
 
 template <typename R, int MX, int MZ>
@@ -614,7 +747,11 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
     pa.kunit = 2.0 * 3.14159265358979323846 / P->L;
     pa.scale = 1.0 / (P->eta * (double)M * M * M);
     mark(0);
-    {
+    if (sizeof(R) == sizeof(float) && M == 256) {
+        using G = XGeom<16, 8>;
+        hipLaunchKernelGGL((k_fft_x_r2c_reg<16, 8>), dim3((nlines + G::LPB - 1) / G::LPB), dim3(G::NT),
+                           0, st, (float*)grid, (const C2<float>*)tw, nlines);
+    } else {
         const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;
         hipLaunchKernelGGL((k_fft_x_r2c<R, MX>), dim3((nlines + P->Wx - 1) / P->Wx),
                            dim3(kFFTThreads), shm, st, grid, tw, M, P->radH, P->Wx, nlines);
@@ -654,7 +791,11 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
                            tw, M, P->radM, P->Wy, lwy);
         mark(4);
     }
-    {
+    if (sizeof(R) == sizeof(float) && M == 256) {
+        using G = XGeom<16, 8>;
+        hipLaunchKernelGGL((k_fft_x_c2r_reg<16, 8>), dim3((nlines + G::LPB - 1) / G::LPB), dim3(G::NT),
+                           0, st, (float*)grid, (const C2<float>*)tw, nlines);
+    } else {
         const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;
         hipLaunchKernelGGL((k_fft_x_c2r<R, MX>), dim3((nlines + P->Wx - 1) / P->Wx),
                            dim3(kFFTThreads), shm, st, grid, tw, M, P->radH, P->Wx, nlines);
