@@ -100,10 +100,12 @@ void choose_tiles(fcm_plan_impl* P) {
     }
     P->TX = bx;
     P->TY = by;
-    const int tzs[] = {16, 12, 8, 6, 4, 2};
-    P->TZ = 2;
+    // tile height: a divisor of M with TZ <= M - MG + 1, so that the heights a
+    // particle's support covers within a tile form a single run
+    const int tzs[] = {16, 12, 8, 6, 4, 2, 1};
+    P->TZ = 1;
     for (int t : tzs)
-        if (M % t == 0) {
+        if (M % t == 0 && t <= M - MG + 1) {
             P->TZ = t;
             break;
         }

@@ -469,9 +469,6 @@ struct RDFT<R, 8, DIR> {
     static __device__ inline void run(C2<R>* x) { DFT<R, 8, DIR>::run(x); }
 };
 
-// raw buffer access (word 3 of the resource: 32-bit data format, as for all
-// gfx9-family raw buffers)
-constexpr int kBufferWord3 = 0x00020000;
 __device__ inline C2<float> buf_load(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
     return __builtin_bit_cast(C2<float>, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
 }

@@ -68,13 +68,31 @@ struct Acc<ACC_WIDE, float> {
     __device__ inline float value() const { return (float)s; }
 };
 
+// contributors staged for one round of the spread, one array per field
+template <typename R>
+struct Stage {
+    int s[3][kChunk];
+    R f[3][kChunk];
+    R F[3][kChunk];
+    R T[3][kChunk];
+    __device__ inline void put(int k, const GridRec<R>& r) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            s[d][k] = r.s[d];
+            f[d][k] = r.f[d];
+            F[d][k] = r.F[d];
+            T[d][k] = r.T[d];
+        }
+    }
+};
+
 template <typename R, int TZ, int MODE, bool TORQUE, bool SAMEW>
 __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ rec,
                                                const int* __restrict__ bin_start,
                                                R* __restrict__ grid, GridArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    GridRec<R>* stg = reinterpret_cast<GridRec<R>*>(smem);
-    ZTab<R>* zt = reinterpret_cast<ZTab<R>*>(smem + kChunk * sizeof(GridRec<R>));
+    Stage<R>& stg = *reinterpret_cast<Stage<R>*>(smem);
+    ZTab<R>* zt = reinterpret_cast<ZTab<R>*>(smem + sizeof(Stage<R>));
 
     const int lane = threadIdx.x;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -128,12 +146,12 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                     }
                     const unsigned long long mask = __ballot(take);
                     const int cnt = __popcll(mask);
-                    if (take) stg[__popcll(mask & ((1ull << lane) - 1ull))] = r;
+                    if (take) stg.put(__popcll(mask & ((1ull << lane) - 1ull)), r);
                     __syncthreads();
                     // 2. their z factors, one table entry per lane
                     for (int e = lane; e < cnt * MG; e += 64) {
                         const int s = (e * a.mgmul) >> 16, t = e - s * MG;
-                        const R d = ((R)t - stg[s].f[2]) * dx;
+                        const R d = ((R)t - stg.f[2][s]) * dx;
                         const R d2 = d * d;
                         ZTab<R> z;
                         z.g = fexp2(-d2 * a.e2);
@@ -145,16 +163,16 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                     __syncthreads();
                     // 3. accumulate
                     for (int q = 0; q < cnt; ++q) {
-                        const int sx = __builtin_amdgcn_readfirstlane(stg[q].s[0]);
-                        const int sy = __builtin_amdgcn_readfirstlane(stg[q].s[1]);
-                        const int sz = __builtin_amdgcn_readfirstlane(stg[q].s[2]);
+                        const int sx = __builtin_amdgcn_readfirstlane(stg.s[0][q]);
+                        const int sy = __builtin_amdgcn_readfirstlane(stg.s[1][q]);
+                        const int sz = __builtin_amdgcn_readfirstlane(stg.s[2][q]);
                         int dxi = gxp - sx;
                         if (dxi < 0) dxi += M;
                         int dyi = gyp - sy;
                         if (dyi < 0) dyi += M;
                         const bool in = lact && dxi < MG && dyi < MG;
-                        const R dxv = ((R)dxi - stg[q].f[0]) * dx;
-                        const R dyv = ((R)dyi - stg[q].f[1]) * dx;
+                        const R dxv = ((R)dxi - stg.f[0][q]) * dx;
+                        const R dyv = ((R)dyi - stg.f[1][q]) * dx;
                         const R x2 = dxv * dxv, y2 = dyv * dyv;
                         const R gxy = in ? fexp2(-(x2 + y2) * a.e2) : (R)0;
                         // Column coefficients: with g_z, d_z the z factors, the
@@ -168,12 +186,12 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                         R P[3], Q[3], Pt[3] = {0, 0, 0}, S0 = 0, S1 = 0;
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            P[c] = wf * stg[q].F[c];
-                            Q[c] = wq * stg[q].F[c];
+                            P[c] = wf * stg.F[c][q];
+                            Q[c] = wq * stg.F[c][q];
                         }
                         if (TORQUE) {
                             const R gxyD = SAMEW ? gxy : (in ? fexp2(-(x2 + y2) * a.e2D) : (R)0);
-                            const R T0 = stg[q].T[0], T1 = stg[q].T[1], T2 = stg[q].T[2];
+                            const R T0 = stg.T[0][q], T1 = stg.T[1][q], T2 = stg.T[2][q];
                             // T x d = (T1 dz - T2 dy, T2 dx - T0 dz, T0 dy - T1 dx)
                             Pt[0] = -gxyD * T2 * dyv;
                             Pt[1] = gxyD * T2 * dxv;
@@ -196,48 +214,48 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                         if (lo2 < TZ) kmask |= ((1u << hi2) - 1u) & ~((1u << lo2) - 1u);
                         kmask = __builtin_amdgcn_readfirstlane(kmask);
                         const ZTab<R>* zq = zt + q * MG;
-#pragma unroll
-                        for (int k = 0; k < TZ; ++k) {
-                            if (kmask & (1u << k)) {
-                                int dzi = dz0 + k;
-                                if (dzi >= M) dzi -= M;
-                                const ZTab<R> e = zq[dzi];
-                                if (MODE == ACC_PLAIN) {
-                                    R v0 = acc[0][k].s, v1 = acc[1][k].s, v2 = acc[2][k].s;
-                                    v0 = v0 + e.g * P[0] + e.gd2 * Q[0];
-                                    v1 = v1 + e.g * P[1] + e.gd2 * Q[1];
-                                    v2 = v2 + e.g * P[2] + e.gd2 * Q[2];
-                                    if (TORQUE) {
-                                        if (!SAMEW) {
-                                            v0 = v0 + e.gD * Pt[0];
-                                            v1 = v1 + e.gD * Pt[1];
-                                            v2 = v2 + e.gD * Pt[2];
-                                        }
-                                        v0 = v0 + e.gDd * S0;
-                                        v1 = v1 + e.gDd * S1;
+                        auto step = [&](const int k, const ZTab<R>& e) {
+                            if (MODE == ACC_PLAIN) {
+                                R v0 = acc[0][k].s, v1 = acc[1][k].s, v2 = acc[2][k].s;
+                                v0 = v0 + e.g * P[0] + e.gd2 * Q[0];
+                                v1 = v1 + e.g * P[1] + e.gd2 * Q[1];
+                                v2 = v2 + e.g * P[2] + e.gd2 * Q[2];
+                                if (TORQUE) {
+                                    if (!SAMEW) {
+                                        v0 = v0 + e.gD * Pt[0];
+                                        v1 = v1 + e.gD * Pt[1];
+                                        v2 = v2 + e.gD * Pt[2];
                                     }
-                                    acc[0][k].s = v0;
-                                    acc[1][k].s = v1;
-                                    acc[2][k].s = v2;
-                                } else {
-                                    R v0 = e.g * P[0] + e.gd2 * Q[0];
-                                    R v1 = e.g * P[1] + e.gd2 * Q[1];
-                                    R v2 = e.g * P[2] + e.gd2 * Q[2];
-                                    if (TORQUE) {
-                                        if (!SAMEW) {
-                                            v0 = v0 + e.gD * Pt[0];
-                                            v1 = v1 + e.gD * Pt[1];
-                                            v2 = v2 + e.gD * Pt[2];
-                                        }
-                                        v0 = v0 + e.gDd * S0;
-                                        v1 = v1 + e.gDd * S1;
-                                    }
-                                    acc[0][k].add(v0);
-                                    acc[1][k].add(v1);
-                                    acc[2][k].add(v2);
+                                    v0 = v0 + e.gDd * S0;
+                                    v1 = v1 + e.gDd * S1;
                                 }
+                                acc[0][k].s = v0;
+                                acc[1][k].s = v1;
+                                acc[2][k].s = v2;
+                            } else {
+                                R v0 = e.g * P[0] + e.gd2 * Q[0];
+                                R v1 = e.g * P[1] + e.gd2 * Q[1];
+                                R v2 = e.g * P[2] + e.gd2 * Q[2];
+                                if (TORQUE) {
+                                    if (!SAMEW) {
+                                        v0 = v0 + e.gD * Pt[0];
+                                        v1 = v1 + e.gD * Pt[1];
+                                        v2 = v2 + e.gD * Pt[2];
+                                    }
+                                    v0 = v0 + e.gDd * S0;
+                                    v1 = v1 + e.gDd * S1;
+                                }
+                                acc[0][k].add(v0);
+                                acc[1][k].add(v1);
+                                acc[2][k].add(v2);
                             }
-                        }
+                        };
+                        // The plan keeps TZ <= M - MG + 1, so the active heights
+                        // are one run and the table entry of height k is zb[k].
+                        const ZTab<R>* zb = zq + (hi1 > 0 ? dz0 : dz0 - M);
+#pragma unroll
+                        for (int k = 0; k < TZ; ++k)
+                            if (kmask & (1u << k)) step(k, zb[k]);
                     }
                     __syncthreads();
                 }
@@ -253,6 +271,29 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
             for (int c = 0; c < 3; ++c) grid[c * M3 + idx] = acc[c][k].value();
         }
     }
+}
+
+// element at byte offset `col` of the M x M plane starting at `plane` (a
+// wavefront-uniform pointer)
+__device__ inline float plane_load(const float* plane, int M, unsigned col) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(plane), (short)0, M * M * (int)sizeof(float), kBufferWord3);
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)col, 0, 0));
+}
+__device__ inline double plane_load(const double* plane, int M, unsigned col) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(plane), (short)0, M * M * (int)sizeof(double), kBufferWord3);
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)col, 0, 0));
+}
+
+__device__ inline float uniform(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ inline double uniform(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
 template <typename R>
@@ -272,7 +313,15 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
     const int lane = threadIdx.x & 63;
     const int p = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
     const bool live = p < a.N;
-    const GridRec<R> r = rec[live ? p : a.N - 1];
+    const GridRec<R> rv = rec[live ? p : a.N - 1];
+    // the record is the same for the whole wavefront: keep it in scalar registers
+    GridRec<R> r;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        r.s[d] = __builtin_amdgcn_readfirstlane(rv.s[d]);
+        r.f[d] = uniform(rv.f[d]);
+    }
+    r.orig = __builtin_amdgcn_readfirstlane(rv.orig);
     const int M = a.M, MG = a.MG;
     const R dx = a.dx;
     if (lane < MG) {
@@ -303,13 +352,17 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
         const R x2 = dxv * dxv, y2 = dyv * dyv;
         const R gxy = ok ? fexp2(-(x2 + y2) * a.e2) : (R)0;
         R A0[3] = {0, 0, 0}, A2[3] = {0, 0, 0}, D1[3] = {0, 0, 0}, D0[3] = {0, 0, 0};
-        const R* colp = grid + (size_t)y * M + x;
+        // per-lane byte offset of the column within a z plane (32 bits); the
+        // plane and component bases are wavefront-uniform
+        const unsigned col = ((unsigned)y * (unsigned)M + (unsigned)x) * (unsigned)sizeof(R);
         for (int k = 0; k < MG; ++k) {
             int z = r.s[2] + k;
             if (z >= M) z -= M;
             const ZTab<R> e = zt[wave][k];
-            const size_t off = (size_t)z * M * M;
-            const R u0 = colp[off], u1 = colp[M3 + off], u2 = colp[2 * M3 + off];
+            const R* pz = grid + (size_t)z * M * M;
+            const R u0 = plane_load(pz, M, col);
+            const R u1 = plane_load(pz + M3, M, col);
+            const R u2 = plane_load(pz + 2 * M3, M, col);
             A0[0] += e.g * u0;
             A0[1] += e.g * u1;
             A0[2] += e.g * u2;
@@ -398,7 +451,7 @@ GridArgs<R> make_args(const fcm_plan_impl* P) {
 template <typename R, int TZ, int MODE, bool TORQUE>
 hipError_t spread_tz(const fcm_plan_impl* P, R* grid, hipStream_t st) {
     GridArgs<R> a = make_args<R>(P);
-    const size_t shm = kChunk * (sizeof(GridRec<R>) + (size_t)P->MG * sizeof(ZTab<R>));
+    const size_t shm = sizeof(Stage<R>) + kChunk * (size_t)P->MG * sizeof(ZTab<R>);
     dim3 g(P->nbins), b(64);
     const GridRec<R>* rec = (const GridRec<R>*)P->grec;
     if (a.same_width)
@@ -417,6 +470,7 @@ hipError_t spread_m(const fcm_plan_impl* P, R* grid, hipStream_t st) {
         case 6: return spread_tz<R, 6, MODE, TORQUE>(P, grid, st);
         case 4: return spread_tz<R, 4, MODE, TORQUE>(P, grid, st);
         case 2: return spread_tz<R, 2, MODE, TORQUE>(P, grid, st);
+        case 1: return spread_tz<R, 1, MODE, TORQUE>(P, grid, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -75,6 +75,12 @@ __host__ __device__ inline unsigned div_magic(unsigned d) {
     return d <= 1 ? 0u : (unsigned)(0x100000000ull / d + 1ull);
 }
 
+// Word 3 of a raw buffer resource (32-bit data format, as for all gfx9-family
+// raw buffers).  Buffer loads address with one 32-bit lane offset plus a
+// scalar offset, so wavefront-uniform parts of an address stay in scalar
+// registers; reads past num_records return 0.
+constexpr int kBufferWord3 = 0x00020000;
+
 __device__ inline int fast_div(int j, int d, unsigned m) {
     return d == 1 ? j : (int)__umulhi((unsigned)j, m);
 }
