@@ -137,7 +137,7 @@ struct fcm_plan_impl {
     int* counts;           // nbins + ncells (+2) counters
     int* starts;           // exclusive scans: bins then cells
     int* keys;             // 2N keys (bin, cell)
-    int* ranks;            // 2N ranks within key
+    int* ranks;            // 2N ranks within key; after the sort, the inverse permutations
     int* perm;             // 2N: grid order then pair order
     int* scan_tmp;         // block sums of the scan
     void* grec;            // N GridRec
@@ -166,12 +166,12 @@ hipError_t launch_hash(const fcm_plan_impl* P, const double* pos, hipStream_t st
 hipError_t launch_scan(const fcm_plan_impl* P, hipStream_t st);
 // counting-sort scatter and in-segment ordering by original index
 hipError_t launch_scatter(const fcm_plan_impl* P, hipStream_t st);
-// gather the sorted per-particle records
+// the per-particle records in sorted order (built from the caller's order)
 hipError_t launch_gather_grid(const fcm_plan_impl* P, const double* pos, const double* F,
                               const double* T, hipStream_t st);
 hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const double* F,
                               const double* T, hipStream_t st);
-// both of the above in one launch (F required)
+// both of the above in one launch
 hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const double* F,
                               const double* T, hipStream_t st);
 

@@ -1,11 +1,13 @@
 // Particle bookkeeping of fast FCM (Sec. 4, spatial hashing and sorting):
 // periodic wrap, hashing into grid bins (for the spreading tiles) and into
 // pair cells of width >= R_c (m = max(int(L/R_c), 3) per axis), a counting
-// sort by key, and the gather of the sorted per-particle records.
+// sort by key, and the per-particle records in sorted order.
 //
 // The counting sort places particles with atomics and then orders every
 // segment by original index, so the sorted order is (key, original index):
-// deterministic from run to run.
+// deterministic from run to run.  The records are built in the caller's
+// order (coalesced reads of positions, forces and torques) and stored at each
+// particle's sorted position through the inverse permutation.
 #include "fcm_internal.h"
 
 namespace fcm {
@@ -190,17 +192,20 @@ __global__ void k_scatter(const int* __restrict__ keys, const int* __restrict__ 
 }
 
 // order each segment of perm by value (insertion sort): segments 0..nbins-1
-// are the grid bins (perm[0..N)), the next ncells the pair cells (perm[N..2N))
+// are the grid bins (perm[0..N)), the next ncells the pair cells (perm[N..2N));
+// then record the inverse permutation: inv[perm[j]] = j (inv[N + ...] for cells)
 __global__ void k_segment_order(const int* __restrict__ starts, int nbins, int ncells, int N,
-                                int* __restrict__ perm) {
+                                int* __restrict__ perm, int* __restrict__ inv) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nbins + ncells) return;
     const int* start = starts;
     int* pm = perm;
+    int* iv = inv;
     if (s >= nbins) {
         s -= nbins;
         start = starts + nbins + 1;
         pm = perm + N;
+        iv = inv + N;
     }
     const int b = start[s], e = start[s + 1];
     for (int i = b + 1; i < e; ++i) {
@@ -212,92 +217,55 @@ __global__ void k_segment_order(const int* __restrict__ starts, int nbins, int n
         }
         pm[j + 1] = v;
     }
+    for (int i = b; i < e; ++i) iv[pm[i]] = i;
 }
 
+// Per-particle records in sorted order, built in the caller's order: thread i
+// reads particle i (coalesced) and writes its grid record to grec[inv[i]] and
+// its pair record to prec[inv[N + i]] (either may be skipped: null).  F may be
+// null (interpolation alone needs only positions).
 template <typename R>
-__global__ void k_gather_grid(const double* __restrict__ pos, const double* __restrict__ F,
-                              const double* __restrict__ T, const int* __restrict__ perm, int N,
-                              int M, int MG, double L, double dx, double normF, double normT,
-                              GridRec<R>* __restrict__ rec) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    int i = perm[j];
+__global__ void k_place(const double* __restrict__ pos, const double* __restrict__ F,
+                        const double* __restrict__ T, const int* __restrict__ inv,
+                        const int* __restrict__ cellkey, int N, int M, int MG, double L, double dx,
+                        double normF, double normT, GridRec<R>* __restrict__ grec,
+                        PairRec* __restrict__ prec, double4* __restrict__ pos4) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
     int bad = 0;
-    GridRec<R> r;
+    double w[3], f[3], t[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double w = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
-        double u = w / dx;
-        int su = support_start(w, dx, MG);
-        r.s[a] = wrap_index(su, M);
-        r.f[a] = (R)(u - (double)su);
-        r.F[a] = F ? (R)(F[3 * (int64_t)i + a] * normF) : (R)0;
-        r.T[a] = T ? (R)(T[3 * (int64_t)i + a] * normT) : (R)0;
+        w[a] = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
+        f[a] = F ? F[3 * (int64_t)i + a] : 0.0;
+        t[a] = T ? T[3 * (int64_t)i + a] : 0.0;
     }
-    r.orig = i;
-    rec[j] = r;
-}
-
-__global__ void k_gather_pair(const double* __restrict__ pos, const double* __restrict__ F,
-                              const double* __restrict__ T, const int* __restrict__ perm,
-                              const int* __restrict__ cellkey, int N, double L,
-                              PairRec* __restrict__ rec, double4* __restrict__ pos4) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    int i = perm[j];
-    int bad = 0;
-    PairRec r;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        r.y[a] = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
-        r.F[a] = F[3 * (int64_t)i + a];
-        r.T[a] = T ? T[3 * (int64_t)i + a] : 0.0;
-    }
-    r.orig = i;
-    r.cell = cellkey[i];
-    rec[j] = r;
-    pos4[j] = make_double4(r.y[0], r.y[1], r.y[2], 0.0);
-}
-
-// both gathers in one launch: threads [0, N) build the grid records, threads
-// [N, 2N) the pair records
-template <typename R>
-__global__ void k_gather_both(const double* __restrict__ pos, const double* __restrict__ F,
-                              const double* __restrict__ T, const int* __restrict__ perm, int N,
-                              int M, int MG, double L, double dx, double normF, double normT,
-                              GridRec<R>* __restrict__ grec, const int* __restrict__ cellkey,
-                              PairRec* __restrict__ prec, double4* __restrict__ pos4) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * N) return;
-    int bad = 0;
-    if (t < N) {
-        const int i = perm[t];
+    if (grec) {
         GridRec<R> r;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double w = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
-            const int su = support_start(w, dx, MG);
+            const int su = support_start(w[a], dx, MG);
             r.s[a] = wrap_index(su, M);
-            r.f[a] = (R)(w / dx - (double)su);
-            r.F[a] = (R)(F[3 * (int64_t)i + a] * normF);
-            r.T[a] = T ? (R)(T[3 * (int64_t)i + a] * normT) : (R)0;
+            r.f[a] = (R)(w[a] / dx - (double)su);
+            r.F[a] = (R)(f[a] * normF);
+            r.T[a] = (R)(t[a] * normT);
         }
         r.orig = i;
-        grec[t] = r;
-    } else {
-        const int j = t - N;
-        const int i = perm[N + j];
+        grec[inv[i]] = r;
+    }
+    if (prec) {
         PairRec r;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            r.y[a] = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
-            r.F[a] = F[3 * (int64_t)i + a];
-            r.T[a] = T ? T[3 * (int64_t)i + a] : 0.0;
+            r.y[a] = w[a];
+            r.F[a] = f[a];
+            r.T[a] = t[a];
         }
         r.orig = i;
         r.cell = cellkey[i];
+        const int j = inv[N + i];
         prec[j] = r;
-        pos4[j] = make_double4(r.y[0], r.y[1], r.y[2], 0.0);
+        pos4[j] = make_double4(w[0], w[1], w[2], 0.0);
     }
 }
 
@@ -349,57 +317,50 @@ hipError_t launch_scatter(const fcm_plan_impl* P, hipStream_t st) {
     const int* sc = P->starts + P->nbins + 1;
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(N, 256)), dim3(256), 0, st, P->keys, P->ranks, sb,
                        sc, P->perm, N);
+    // the ranks are dead after the scatter: their buffer takes the inverse permutation
     hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(P->nbins + P->ncells, 256)), dim3(256), 0,
-                       st, P->starts, P->nbins, P->ncells, N, P->perm);
+                       st, P->starts, P->nbins, P->ncells, N, P->perm, P->ranks);
     return hipGetLastError();
 }
 
-hipError_t launch_gather_grid(const fcm_plan_impl* P, const double* pos, const double* F,
-                              const double* T, hipStream_t st) {
-    int N = (int)P->N;
-    const double pi = 3.14159265358979323846;
-    double normF = pow(2.0 * pi * P->Sigma * P->Sigma, -1.5);
-    double normT = pow(2.0 * pi * P->SigmaD * P->SigmaD, -1.5) / (2.0 * P->SigmaD * P->SigmaD);
-    if (P->precision == FCM_FP64)
-        hipLaunchKernelGGL(k_gather_grid<double>, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos,
-                           F, T, P->perm, N, P->M, P->MG, P->L, P->dx, normF, normT,
-                           (GridRec<double>*)P->grec);
-    else
-        hipLaunchKernelGGL(k_gather_grid<float>, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos,
-                           F, T, P->perm, N, P->M, P->MG, P->L, P->dx, normF, normT,
-                           (GridRec<float>*)P->grec);
-    return hipGetLastError();
-}
+namespace {
 
-hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const double* F,
-                              const double* T, hipStream_t st) {
-    int N = (int)P->N;
-    hipLaunchKernelGGL(k_gather_pair, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, F, T,
-                       P->perm + N, P->keys + N, N, P->L, P->prec, P->ppos);
-    return hipGetLastError();
-}
-
-}  // namespace fcm
-
-namespace fcm {
-
-hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const double* F,
-                              const double* T, hipStream_t st) {
+// records of the particles in sorted order: grid (`grid`) and/or pair (`pair`)
+hipError_t place(const fcm_plan_impl* P, const double* pos, const double* F, const double* T,
+                 bool grid, bool pair, hipStream_t st) {
     const int N = (int)P->N;
     const double pi = 3.14159265358979323846;
     const double normF = pow(2.0 * pi * P->Sigma * P->Sigma, -1.5);
     const double normT =
         pow(2.0 * pi * P->SigmaD * P->SigmaD, -1.5) / (2.0 * P->SigmaD * P->SigmaD);
-    const dim3 g(blocks_for(2 * (int64_t)N, 256)), b(256);
+    const dim3 g(blocks_for(N, 256)), b(256);
+    PairRec* pr = pair ? P->prec : nullptr;
     if (P->precision == FCM_FP64)
-        hipLaunchKernelGGL(k_gather_both<double>, g, b, 0, st, pos, F, T, P->perm, N, P->M, P->MG,
-                           P->L, P->dx, normF, normT, (GridRec<double>*)P->grec, P->keys + N,
-                           P->prec, P->ppos);
+        hipLaunchKernelGGL(k_place<double>, g, b, 0, st, pos, F, T, P->ranks, P->keys + N, N, P->M,
+                           P->MG, P->L, P->dx, normF, normT,
+                           grid ? (GridRec<double>*)P->grec : nullptr, pr, P->ppos);
     else
-        hipLaunchKernelGGL(k_gather_both<float>, g, b, 0, st, pos, F, T, P->perm, N, P->M, P->MG,
-                           P->L, P->dx, normF, normT, (GridRec<float>*)P->grec, P->keys + N,
-                           P->prec, P->ppos);
+        hipLaunchKernelGGL(k_place<float>, g, b, 0, st, pos, F, T, P->ranks, P->keys + N, N, P->M,
+                           P->MG, P->L, P->dx, normF, normT,
+                           grid ? (GridRec<float>*)P->grec : nullptr, pr, P->ppos);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gather_grid(const fcm_plan_impl* P, const double* pos, const double* F,
+                              const double* T, hipStream_t st) {
+    return place(P, pos, F, T, true, false, st);
+}
+
+hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const double* F,
+                              const double* T, hipStream_t st) {
+    return place(P, pos, F, T, false, true, st);
+}
+
+hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const double* F,
+                              const double* T, hipStream_t st) {
+    return place(P, pos, F, T, true, true, st);
 }
 
 }  // namespace fcm
