@@ -107,6 +107,9 @@ struct PairArgs {
     double eta, sigma, sigmaD, Sigma, SigmaD;
     double selfVF, selfOT;
     int with_pairs;                // 0 = only self corrections (R_c = 0)
+    // the six Gaussian widths of the corrections: squared width s, erfc
+    // argument scale 1/sqrt(2 s), exponent scale -1/(2 s), norm (2 pi s)^(-3/2)
+    double wsq[6], escale[6], gexp[6], gnorm[6];
 };
 
 }  // namespace fcm

@@ -33,36 +33,44 @@ namespace fcm {
 
 namespace {
 
-__device__ inline double gauss3(double r2, double s2) {
-    // (2 pi s2)^(-3/2) exp(-r2 / 2 s2)
-    const double pi = 3.14159265358979323846;
-    const double t = 2.0 * pi * s2;
-    return exp(-0.5 * r2 / s2) / (t * sqrt(t));
-}
+// The six Gaussian widths of the corrections (squared): s1 = 2 sigma^2,
+// s2 = 2 Sigma^2 (force); sa = sigma^2 + sigma_D^2, sb = Sigma^2 + Sigma_D^2
+// (rotation-force); sc = 2 sigma_D^2, sd = 2 Sigma_D^2 (rotation-torque).
+// For each, E(r) = erfc(r / sqrt(2 s)) and D(r) = (2 pi s)^(-3/2) exp(-r^2 / 2 s),
+// with the width constants computed on the host.  When Sigma_D = Sigma the
+// widths sb and sd equal s2 and their terms are shared (SAME).
+enum { W1 = 0, W2, WA, WB, WC, WD };
 
 struct Coef {
     double Avf, Bvf, fof, Aot, Bot;
 };
 
+template <bool SAME>
 __device__ inline Coef correction_coeffs(double r, const PairArgs& a) {
     const double pi = 3.14159265358979323846;
     const double eta = a.eta;
-    const double sg2 = a.sigma * a.sigma, Sg2 = a.Sigma * a.Sigma;
-    const double sD2 = a.sigmaD * a.sigmaD, SD2 = a.SigmaD * a.SigmaD;
     const double r2 = r * r, r3 = r2 * r;
-    const double d = sg2 - Sg2;
+    const double d = a.sigma * a.sigma - a.Sigma * a.Sigma;
+    auto E = [&](int w) { return erfc(r * a.escale[w]); };
+    auto D = [&](int w) { return a.gnorm[w] * exp(r2 * a.gexp[w]); };
+    const double E2 = E(W2), D2 = D(W2);
+    const double Eb = SAME ? E2 : E(WB), Db = SAME ? D2 : D(WB);
+    const double Ed = SAME ? E2 : E(WD), Dd = SAME ? D2 : D(WD);
+    const double s1 = a.wsq[W1], s2 = a.wsq[W2], sa = a.wsq[WA], sb = a.wsq[WB];
+    const double sc = a.wsq[WC], sd = a.wsq[WD];
+    const double i8 = 1.0 / (8.0 * pi * eta * r3);
+    const double ih = 1.0 / (2.0 * eta * r2);
     Coef c;
     // force-velocity: erf part = (E(r; sigma sqrt2) - E(r; Sigma sqrt2)) (G + sigma^2 lap G)
     {
-        const double dE = erfc(r / (2.0 * a.Sigma)) - erfc(r / (2.0 * a.sigma));
+        const double dE = E2 - E(W1);
         const double g1 = 1.0 / (8.0 * pi * eta * r);
-        const double g3 = sg2 / (4.0 * pi * eta * r3);
+        const double g3 = 2.0 * a.sigma * a.sigma * i8;  // sigma^2 / (4 pi eta r^3)
         c.Avf = dE * (g1 + g3);
         c.Bvf = dE * (g1 - 3.0 * g3);
-        const double s1 = 2.0 * sg2, s2 = 2.0 * Sg2;  // squared widths sigma sqrt2, Sigma sqrt2
-        const double D1 = gauss3(r2, s1), D2 = gauss3(r2, s2);
+        const double D1 = D(W1);
         // S3(s1) - S3(s2), S3 = -(s^4 / 2 eta r^2) (I - 3 xh xh) Delta
-        const double t3 = (s1 * s1 * D1 - s2 * s2 * D2) / (2.0 * eta * r2);
+        const double t3 = (s1 * s1 * D1 - s2 * s2 * D2) * ih;
         c.Avf += -t3;
         c.Bvf += 3.0 * t3;
         // -(sigma^2 - Sigma^2) Q2(s2), Q2 = -(1/eta)[(1 + s^2/r^2) I - (1 + 3 s^2/r^2) xh xh] Delta
@@ -75,20 +83,16 @@ __device__ inline Coef correction_coeffs(double r, const PairArgs& a) {
     }
     // rotation-force: R(sa) - R(sb) - (d/2) K(sb)
     {
-        const double sa = sg2 + sD2, sb = Sg2 + SD2;
-        const double dE = erfc(r / sqrt(2.0 * sb)) - erfc(r / sqrt(2.0 * sa));
-        const double Da = gauss3(r2, sa), Db = gauss3(r2, sb);
-        c.fof = (dE - 4.0 * pi * r * (sa * Da - sb * Db)) / (8.0 * pi * eta * r3) +
-                d * Db / (4.0 * eta * sb);
+        const double dE = Eb - E(WA);
+        const double Da = D(WA);
+        c.fof = (dE - 4.0 * pi * r * (sa * Da - sb * Db)) * i8 + d * Db / (4.0 * eta * sb);
     }
     // rotation-torque: (P(sigma_D sqrt2) - P(Sigma_D sqrt2)) / 2
     {
-        const double sc = 2.0 * sD2, sd = 2.0 * SD2;
-        const double dE = erfc(r / (2.0 * a.SigmaD)) - erfc(r / (2.0 * a.sigmaD));
-        const double Dc = gauss3(r2, sc), Dd = gauss3(r2, sd);
-        c.Aot = 0.5 * (-dE / (8.0 * pi * eta * r3) + ((sc + r2) * Dc - (sd + r2) * Dd) / (2.0 * eta * r2));
-        c.Bot = 0.5 * (3.0 * dE / (8.0 * pi * eta * r3) -
-                       ((3.0 * sc + r2) * Dc - (3.0 * sd + r2) * Dd) / (2.0 * eta * r2));
+        const double dE = Ed - E(WC);
+        const double Dc = D(WC);
+        c.Aot = 0.5 * (-dE * i8 + ((sc + r2) * Dc - (sd + r2) * Dd) * ih);
+        c.Bot = 0.5 * (3.0 * dE * i8 - ((3.0 * sc + r2) * Dc - (3.0 * sd + r2) * Dd) * ih);
     }
     return c;
 }
@@ -99,6 +103,7 @@ constexpr int kPairBlock = 256;                   // launched threads (the last 
 constexpr int kScanBlock = 256;
 
 // add the corrections from one neighbour m at x = Y_n - Y_m (r^2 = r2 < R_c^2)
+template <bool SAME>
 __device__ inline void add_pair(double x0, double x1, double x2, double r2, const PairRec& o,
                                 const PairArgs& a, double* v, double* w) {
     const double F0 = o.F[0], F1 = o.F[1], F2 = o.F[2];
@@ -114,7 +119,7 @@ __device__ inline void add_pair(double x0, double x1, double x2, double r2, cons
         w[2] += a.selfOT * T2;
         return;
     }
-    const Coef c = correction_coeffs(r, a);
+    const Coef c = correction_coeffs<SAME>(r, a);
     const double h0 = x0 / r, h1 = x1 / r, h2 = x2 / r;
     const double hF = h0 * F0 + h1 * F1 + h2 * F2;
     const double hT = h0 * T0 + h1 * T1 + h2 * T2;
@@ -210,6 +215,7 @@ __global__ __launch_bounds__(kScanBlock) void k_pair_scan(const double4* __restr
     count[t] = n;
 }
 
+template <bool SAME>
 __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restrict__ pos4,
                                                           const PairRec* __restrict__ rec,
                                                           const int* __restrict__ cell_start,
@@ -265,7 +271,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restr
             const int q = hits[(t0 + lo) * kPairCap + (e - qoff[lo])];
             const double4 y = min_image(pos4[base + lo / 3], pos4[q], L, iL);
             double rv[3] = {0, 0, 0}, rw[3] = {0, 0, 0};
-            add_pair(y.x, y.y, y.z, y.w, rec[q], a, rv, rw);
+            add_pair<SAME>(y.x, y.y, y.z, y.w, rec[q], a, rv, rw);
             res[tid][0] = rv[0];
             res[tid][1] = rv[1];
             res[tid][2] = rv[2];
@@ -297,7 +303,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restr
         scan_layer(pos4, cell_start, a, j, mp, rec[j].cell, layer, [&](int q) {
             if (k++ >= kPairCap) {
                 const double4 y = min_image(mp, pos4[q], L, iL);
-                add_pair(y.x, y.y, y.z, y.w, rec[q], a, pv, pw);
+                add_pair<SAME>(y.x, y.y, y.z, y.w, rec[q], a, pv, pw);
             }
         });
     }
@@ -355,8 +361,24 @@ hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torq
     if (a.with_pairs)
         hipLaunchKernelGGL(k_pair_scan, dim3((3 * a.N + kScanBlock - 1) / kScanBlock), dim3(kScanBlock),
                            0, st, P->ppos, P->prec, cs, a, P->pair_hits, P->pair_count);
-    hipLaunchKernelGGL(k_pair_eval, dim3((a.N + kPairPerBlock - 1) / kPairPerBlock), dim3(kPairBlock),
-                       0, st, P->ppos, P->prec, cs, P->pair_hits, P->pair_count, a, V, W);
+    // width constants of the six Gaussians (see correction_coeffs)
+    const double pi = 3.14159265358979323846;
+    const double sg2 = P->sigma * P->sigma, Sg2 = P->Sigma * P->Sigma;
+    const double sD2 = P->sigmaD * P->sigmaD, SD2 = P->SigmaD * P->SigmaD;
+    const double wsq[6] = {2.0 * sg2, 2.0 * Sg2, sg2 + sD2, Sg2 + SD2, 2.0 * sD2, 2.0 * SD2};
+    for (int k = 0; k < 6; ++k) {
+        a.wsq[k] = wsq[k];
+        a.escale[k] = 1.0 / sqrt(2.0 * wsq[k]);
+        a.gexp[k] = -0.5 / wsq[k];
+        a.gnorm[k] = pow(2.0 * pi * wsq[k], -1.5);
+    }
+    const dim3 ge((a.N + kPairPerBlock - 1) / kPairPerBlock), be(kPairBlock);
+    if (P->SigmaD == P->Sigma)
+        hipLaunchKernelGGL(k_pair_eval<true>, ge, be, 0, st, P->ppos, P->prec, cs, P->pair_hits,
+                           P->pair_count, a, V, W);
+    else
+        hipLaunchKernelGGL(k_pair_eval<false>, ge, be, 0, st, P->ppos, P->prec, cs, P->pair_hits,
+                           P->pair_count, a, V, W);
     return hipGetLastError();
 }
 
