@@ -691,7 +691,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c_reg(float* __restrict__ grid,
     }
 }
 
-template <int N1, int N2>
+template <int N1, int N2, bool TILED>
 __global__ __launch_bounds__(256) void k_fft_x_c2r_reg(float* __restrict__ grid,
                                                        const C2<float>* __restrict__ twg, int nlines) {
     using G = XGeom<N1, N2>;
@@ -725,13 +725,25 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r_reg(float* __restrict__ grid,
         z[i] = C2<float>{Ev.x - O.y, Ev.y + O.x};
     }
     xfft_two_step<N1, N2, 1>(z, tw, E + ll * G::LS, q);
+    if (TILED) {
+        // tiles of 8 x by 4 y: a block's lines are 32 consecutive y of one plane
+        constexpr int M = G::M;
+        const int y = line % M;
+        float* pl = grid + (size_t)(line / M) * M * M + (size_t)(y >> 2) * (M << 2) + ((y & 3) << 3);
 #pragma unroll
-    for (int i = 0; i < N1; ++i)
-        if (ok) g[q + T * i] = z[i];
+        for (int i = 0; i < N1; ++i) {
+            const int x = 2 * (q + T * i);
+            if (ok) *reinterpret_cast<C2<float>*>(pl + ((x >> 3) << 5) + (x & 7)) = z[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N1; ++i)
+            if (ok) g[q + T * i] = z[i];
+    }
 }
 
 template <typename R, int MX, int MZ>
-hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* ev) {
+hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* ev, bool tiled) {
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
@@ -790,8 +802,12 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
     }
     if (sizeof(R) == sizeof(float) && M == 256) {
         using G = XGeom<16, 8>;
-        hipLaunchKernelGGL((k_fft_x_c2r_reg<16, 8>), dim3((nlines + G::LPB - 1) / G::LPB), dim3(G::NT),
-                           0, st, (float*)grid, (const C2<float>*)tw, nlines);
+        if (tiled)
+            hipLaunchKernelGGL((k_fft_x_c2r_reg<16, 8, true>), dim3((nlines + G::LPB - 1) / G::LPB),
+                               dim3(G::NT), 0, st, (float*)grid, (const C2<float>*)tw, nlines);
+        else
+            hipLaunchKernelGGL((k_fft_x_c2r_reg<16, 8, false>), dim3((nlines + G::LPB - 1) / G::LPB),
+                               dim3(G::NT), 0, st, (float*)grid, (const C2<float>*)tw, nlines);
     } else {
         const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;
         hipLaunchKernelGGL((k_fft_x_c2r<R, MX>), dim3((nlines + P->Wx - 1) / P->Wx),
@@ -809,9 +825,12 @@ int fft_maxe(int precision, bool zpass) {
     return zpass ? 8 : 16;
 }
 
-hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st, hipEvent_t* ev) {
-    if (P->precision == FCM_FP64) return solve_r<double, 8, 4>(P, (double*)grid, st, ev);
-    return solve_r<float, 16, 8>(P, (float*)grid, st, ev);
+bool solve_tiles(const fcm_plan_impl* P) { return P->precision != FCM_FP64 && P->M == 256; }
+
+hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st, hipEvent_t* ev,
+                        bool tiled) {
+    if (P->precision == FCM_FP64) return solve_r<double, 8, 4>(P, (double*)grid, st, ev, false);
+    return solve_r<float, 16, 8>(P, (float*)grid, st, ev, tiled && solve_tiles(P));
 }
 
 }  // namespace fcm

@@ -354,7 +354,10 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
         R A0[3] = {0, 0, 0}, A2[3] = {0, 0, 0}, D1[3] = {0, 0, 0}, D0[3] = {0, 0, 0};
         // per-lane byte offset of the column within a z plane (32 bits); the
         // plane and component bases are wavefront-uniform
-        const unsigned col = ((unsigned)y * (unsigned)M + (unsigned)x) * (unsigned)sizeof(R);
+        const unsigned col =
+            (a.tiled ? (unsigned)((y >> 2) * (M << 2) + ((x >> 3) << 5) + ((y & 3) << 3) + (x & 7))
+                     : (unsigned)y * (unsigned)M + (unsigned)x) *
+            (unsigned)sizeof(R);
         for (int k = 0; k < MG; ++k) {
             int z = r.s[2] + k;
             if (z >= M) z -= M;
@@ -419,6 +422,135 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
     }
 }
 
+__device__ inline float4 plane_load4(const float* plane, int M, unsigned col) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(plane), (short)0, M * M * (int)sizeof(float), kBufferWord3);
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)col, 0, 0));
+}
+
+// FP32 interpolation with 16-byte loads (M divisible by 4, M_G <= 13, Sigma_D =
+// Sigma): lane (j, c) owns support row j and the aligned chunk c of four x
+// points, so each load returns four values of one row and a wavefront covers a
+// particle's support in one pass.  Per z plane the lane forms the x-weighted
+// sums of its chunk; the z sums and the lane sums follow the factorisation
+//   V_c     = (A + B dy^2) P_c + B (R_c + PD2_c)
+//   Omega   = (dy P_z - PD_y, PD_x - Q_z, Q_y - dy P_x)
+// with P_c = sum_z g_z sum_x g_xy u_c, R_c = sum_z g_z sum_x g_xy dx^2 u_c,
+// PD2_c = sum_z g_z dz^2 sum_x g_xy u_c, PD_c = sum_z g_z dz sum_x g_xy u_c,
+// Q_c = sum_z g_z sum_x g_xy dx u_c.
+template <bool OMEGA>
+__global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restrict__ rec,
+                                                 const float* __restrict__ grid, double* __restrict__ V,
+                                                 double* __restrict__ W, GridArgs<float> a,
+                                                 double scaleV, double scaleW) {
+    __shared__ ZTab<float> zt[4][kMaxSupport];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int p = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const bool live = p < a.N;
+    const GridRec<float> rv = rec[live ? p : a.N - 1];
+    GridRec<float> r;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        r.s[d] = __builtin_amdgcn_readfirstlane(rv.s[d]);
+        r.f[d] = uniform(rv.f[d]);
+    }
+    r.orig = __builtin_amdgcn_readfirstlane(rv.orig);
+    const int M = a.M, MG = a.MG;
+    const float dx = a.dx;
+    if (lane < MG) {
+        const float d = ((float)lane - r.f[2]) * dx;
+        const float d2 = d * d;
+        ZTab<float> e;
+        e.g = fexp2(-d2 * a.e2);
+        e.gd2 = e.g * d2;
+        e.gD = e.g;
+        e.gDd = e.g * d;
+        zt[wave][lane] = e;
+    }
+    // lane -> support row j, chunk c of four x points starting at the aligned x0 & ~3
+    const int j = lane >> 2, c = lane & 3;
+    const int x0 = r.s[0], off0 = x0 & 3;
+    int xs = (x0 - off0) + 4 * c;
+    if (xs >= M) xs -= M;
+    const bool rowok = j < MG;
+    int yy = r.s[1] + (rowok ? j : 0);
+    if (yy >= M) yy -= M;
+    const float dyv = ((float)j - r.f[1]) * dx;
+    const float gy = rowok ? fexp2(-dyv * dyv * a.e2) : 0.0f;
+    float gw[4], gwd[4], gwd2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int i = 4 * c + e - off0;
+        const float dxe = ((float)i - r.f[0]) * dx;
+        const float gx = (i >= 0 && i < MG) ? fexp2(-dxe * dxe * a.e2) : 0.0f;
+        gw[e] = gx * gy;
+        gwd[e] = gw[e] * dxe;
+        gwd2[e] = gwd[e] * dxe;
+    }
+    const unsigned col =
+        (a.tiled ? (unsigned)((yy >> 2) * (M << 2) + ((xs >> 3) << 5) + ((yy & 3) << 3) + (xs & 7))
+                 : (unsigned)yy * (unsigned)M + (unsigned)xs) *
+        4u;
+    __syncthreads();
+    const size_t M3 = (size_t)M * M * M;
+    float P[3] = {0, 0, 0}, Rr[3] = {0, 0, 0}, PD2[3] = {0, 0, 0}, PD[2] = {0, 0}, Q[2] = {0, 0};
+    for (int k = 0; k < MG; ++k) {
+        int z = r.s[2] + k;
+        if (z >= M) z -= M;
+        const ZTab<float> e = zt[wave][k];
+        const float* pz = grid + (size_t)z * M * M;
+        float4 u[3];
+        u[0] = plane_load4(pz, M, col);
+        u[1] = plane_load4(pz + M3, M, col);
+        u[2] = plane_load4(pz + 2 * M3, M, col);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const float pc = gw[0] * u[cc].x + gw[1] * u[cc].y + gw[2] * u[cc].z + gw[3] * u[cc].w;
+            const float rc = gwd2[0] * u[cc].x + gwd2[1] * u[cc].y + gwd2[2] * u[cc].z + gwd2[3] * u[cc].w;
+            P[cc] += e.g * pc;
+            Rr[cc] += e.g * rc;
+            PD2[cc] += e.gd2 * pc;
+            if (OMEGA) {
+                if (cc < 2) PD[cc] += e.gDd * pc;
+                if (cc > 0) {
+                    const float qc = gwd[0] * u[cc].x + gwd[1] * u[cc].y + gwd[2] * u[cc].z + gwd[3] * u[cc].w;
+                    Q[cc - 1] += e.g * qc;
+                }
+            }
+        }
+    }
+    const float cy = a.A + a.B * dyv * dyv;
+    float v0 = cy * P[0] + a.B * (Rr[0] + PD2[0]);
+    float v1 = cy * P[1] + a.B * (Rr[1] + PD2[1]);
+    float v2 = cy * P[2] + a.B * (Rr[2] + PD2[2]);
+    float o0 = 0, o1 = 0, o2 = 0;
+    if (OMEGA) {
+        o0 = dyv * P[2] - PD[1];
+        o1 = PD[0] - Q[1];
+        o2 = Q[0] - dyv * P[0];
+    }
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    v2 = wave_sum(v2);
+    if (OMEGA) {
+        o0 = wave_sum(o0);
+        o1 = wave_sum(o1);
+        o2 = wave_sum(o2);
+    }
+    if (live && lane == 0) {
+        const int64_t n = r.orig;
+        V[3 * n + 0] = (double)v0 * scaleV;
+        V[3 * n + 1] = (double)v1 * scaleV;
+        V[3 * n + 2] = (double)v2 * scaleV;
+        if (OMEGA) {
+            W[3 * n + 0] = (double)o0 * scaleW;
+            W[3 * n + 1] = (double)o1 * scaleW;
+            W[3 * n + 2] = (double)o2 * scaleW;
+        }
+    }
+}
+
 template <typename R>
 GridArgs<R> make_args(const fcm_plan_impl* P) {
     GridArgs<R> a;
@@ -435,6 +567,7 @@ GridArgs<R> make_args(const fcm_plan_impl* P) {
     a.backy = P->backy;
     a.backz = P->backz;
     a.mgmul = 65536 / P->MG + 1;
+    a.tiled = 0;
     a.dx = (R)P->dx;
     const double log2e = 1.4426950408889634074;
     a.e2 = (R)(log2e / (2.0 * P->Sigma * P->Sigma));
@@ -481,8 +614,10 @@ hipError_t spread_r(const fcm_plan_impl* P, bool torque, R* grid, hipStream_t st
 }
 
 template <typename R>
-hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W, hipStream_t st) {
+hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W, hipStream_t st,
+                    bool tiled) {
     GridArgs<R> a = make_args<R>(P);
+    a.tiled = tiled ? 1 : 0;
     const double pi = 3.14159265358979323846;
     const double dV = P->dx * P->dx * P->dx;
     const double scaleV = dV * pow(2.0 * pi * P->Sigma * P->Sigma, -1.5);
@@ -490,6 +625,15 @@ hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W,
         dV * pow(2.0 * pi * P->SigmaD * P->SigmaD, -1.5) / (2.0 * P->SigmaD * P->SigmaD);
     dim3 g((unsigned)((P->N + 3) / 4)), b(256);
     const GridRec<R>* rec = (const GridRec<R>*)P->grec;
+    if constexpr (sizeof(R) == sizeof(float)) {
+        if (P->M % 4 == 0 && P->MG <= 13 && a.same_width) {
+            if (W == nullptr)
+                hipLaunchKernelGGL(k_interp4<false>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+            else
+                hipLaunchKernelGGL(k_interp4<true>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+            return hipGetLastError();
+        }
+    }
     if (W == nullptr)
         hipLaunchKernelGGL((k_interp<R, false, true>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
     else if (a.same_width)
@@ -509,9 +653,9 @@ hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStr
 }
 
 hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, double* W,
-                         hipStream_t st) {
-    if (P->precision == FCM_FP64) return interp_r<double>(P, (const double*)grid, V, W, st);
-    return interp_r<float>(P, (const float*)grid, V, W, st);
+                         hipStream_t st, bool tiled) {
+    if (P->precision == FCM_FP64) return interp_r<double>(P, (const double*)grid, V, W, st, tiled);
+    return interp_r<float>(P, (const float*)grid, V, W, st, tiled);
 }
 
 }  // namespace fcm

@@ -93,6 +93,7 @@ struct GridArgs {
     int nbx, nby, nbz;             // tiles (= bins) per axis
     int backx, backy, backz;       // bins scanned before the tile's own
     int mgmul;                     // 65536 / MG + 1: e / MG = (e * mgmul) >> 16 for e < 1024
+    int tiled;                     // interp: field in the x-y tiled layout
     R dx;                          // grid spacing
     R e2;                          // log2(e) / (2 Sigma^2)
     R e2D;                         // log2(e) / (2 Sigma_D^2)
@@ -179,11 +180,16 @@ hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const d
                               const double* T, hipStream_t st);
 
 hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st);
+// tiled: the field is in the x-y tiled layout written by launch_solve(..., tiled)
 hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, double* W,
-                         hipStream_t st);
+                         hipStream_t st, bool tiled = false);
 // ev: NULL or 6 events recorded before/between/after the five FFT passes
+// tiled: write the velocity field in the x-y tiled layout (tiles of 8 x by 4 y,
+// x fastest inside a tile, tiles x fastest, then tile rows, then z) when the
+// plan supports it (solve_tiles); the result says whether it did
 hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st,
-                        hipEvent_t* ev = nullptr);
+                        hipEvent_t* ev = nullptr, bool tiled = false);
+bool solve_tiles(const fcm_plan_impl* P);
 hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool torque,
                        hipStream_t st);
 
