@@ -492,6 +492,8 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
         (a.tiled ? (unsigned)((yy >> 2) * (M << 2) + ((xs >> 3) << 5) + ((yy & 3) << 3) + (xs & 7))
                  : (unsigned)yy * (unsigned)M + (unsigned)xs) *
         4u;
+    // lanes whose row or chunk lies outside the support load nothing
+    const bool need = rowok && 4 * c - off0 < MG && 4 * c + 3 - off0 >= 0;
     __syncthreads();
     const size_t M3 = (size_t)M * M * M;
     float P[3] = {0, 0, 0}, Rr[3] = {0, 0, 0}, PD2[3] = {0, 0, 0}, PD[2] = {0, 0}, Q[2] = {0, 0};
@@ -500,10 +502,12 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
         if (z >= M) z -= M;
         const ZTab<float> e = zt[wave][k];
         const float* pz = grid + (size_t)z * M * M;
-        float4 u[3];
-        u[0] = plane_load4(pz, M, col);
-        u[1] = plane_load4(pz + M3, M, col);
-        u[2] = plane_load4(pz + 2 * M3, M, col);
+        float4 u[3] = {make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0)};
+        if (need) {
+            u[0] = plane_load4(pz, M, col);
+            u[1] = plane_load4(pz + M3, M, col);
+            u[2] = plane_load4(pz + 2 * M3, M, col);
+        }
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
             const float pc = gw[0] * u[cc].x + gw[1] * u[cc].y + gw[2] * u[cc].z + gw[3] * u[cc].w;
