@@ -68,6 +68,9 @@ struct Acc<ACC_WIDE, float> {
     __device__ inline float value() const { return (float)s; }
 };
 
+// the n lowest bits set (0 <= n <= 32)
+__device__ inline unsigned low_bits(int n) { return n >= 32 ? 0xffffffffu : (1u << n) - 1u; }
+
 // contributors staged for one round of the spread, one array per field
 template <typename R>
 struct Stage {
@@ -210,8 +213,8 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                         const int hi1 = min(TZ, MG - dz0);
                         const int lo2 = M - dz0;
                         const int hi2 = min(TZ, M - dz0 + MG);
-                        unsigned kmask = hi1 > 0 ? (1u << hi1) - 1u : 0u;
-                        if (lo2 < TZ) kmask |= ((1u << hi2) - 1u) & ~((1u << lo2) - 1u);
+                        unsigned kmask = hi1 > 0 ? low_bits(hi1) : 0u;
+                        if (lo2 < TZ) kmask |= low_bits(hi2) & ~low_bits(lo2);
                         kmask = __builtin_amdgcn_readfirstlane(kmask);
                         const ZTab<R>* zq = zt + q * MG;
                         auto step = [&](const int k, const ZTab<R>& e) {
