@@ -359,16 +359,17 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__
     }
 }
 
-// ---- register-resident transforms for M = N1 N2 (FP32) ----
+// ---- register-resident transforms (FP32) ----
 //
-// A length-M transform of W adjacent columns is done by W N2 threads: thread
-// (w, p) holds the N1 elements x[j1 N2 + p] of column w, transforms them in
-// registers (an N1-point DFT), multiplies by exp(+-2 pi i p k1 / M), and one
-// LDS exchange hands thread (w, k1) the N2 values of index k1; an N2-point DFT
-// in registers then gives X[k1 + N1 k2] (four-step Cooley-Tukey).  The inverse
-// used after the projection runs the same steps in the opposite order, from
-// that spectral layout back to x[a + N2 b] in thread (w, a).  Each element
-// crosses LDS once per transform instead of once per radix stage.
+// A transform of length N = N1 N2 (N2 dividing N1, C = N1 / N2) is done by N2
+// threads per line: thread p holds the N1 elements x[p + N2 j], transforms
+// them in registers (an N1-point DFT), multiplies by exp(+-2 pi i p k1 / N),
+// and one LDS exchange hands it the N2 values of each of the C indices
+// k1 = p + N2 s; C N2-point DFTs in registers give X[k1 + N1 k2] = X[p + N2 i]
+// with i = s + C k2 (four-step Cooley-Tukey).  Input and output share the
+// layout "thread p holds the indices congruent to p modulo N2", so the same
+// routine runs forward and inverse transforms in either pass order.  Each
+// element crosses LDS once per transform instead of once per radix stage.
 
 // cos and sin of 2 pi m / n at compile time: exact quadrant reduction, then
 // Taylor series on [0, pi/2)
@@ -477,63 +478,53 @@ __device__ inline void buf_store(C2<float> v, __amdgpu_buffer_rsrc_t rs, int vof
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), rs, voff, soff, 0);
 }
 
-template <int N1, int N2, int W>
-struct RegGeom {
-    static_assert(N1 == N2, "square split only");
-    static constexpr int M = N1 * N2;
-    static constexpr int H = M / 2;
-    static constexpr int NT = W * N2;        // threads per block
-    static constexpr int PL = N2 * W + 8;    // exchange-buffer plane stride (complex)
-    static constexpr int NG = H / W;         // column groups per row of kx
-    static_assert(H % W == 0, "W must divide M/2");
-};
-
-// thread (w, p): v[j1] = x[j1 N2 + p]  ->  v[k2] = X[p + N1 k2]
-template <int N1, int N2, int W, int DIR>
-__device__ inline void reg_fft_fwd(C2<float>* v, const C2<float>* tw, C2<float>* E, int w, int p) {
-    using G = RegGeom<N1, N2, W>;
+// One four-step transform per thread group (see above).  v: in v[j] =
+// x[p + N2 j], out v[i] = X[p + N2 i].  tw: table of exp(-2 pi i m / (N TS)).
+// E: this group's exchange buffer; element (k1, p) at E[k1 ES + p EP].
+template <int N1, int N2, int DIR, int TS>
+__device__ inline void four_step(C2<float>* v, const C2<float>* tw, C2<float>* E, int p, int ES,
+                                 int EP) {
+    constexpr int C = N1 / N2;
+    static_assert(C * N2 == N1, "N2 must divide N1");
     RDFT<float, N1, DIR>::run(v);
 #pragma unroll
     for (int k1 = 1; k1 < N1; ++k1) {
-        C2<float> t = tw[p * k1];
+        C2<float> t = tw[p * k1 * TS];
         if (DIR > 0) t.y = -t.y;
         v[k1] = cmul(v[k1], t);
     }
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) E[k1 * G::PL + p * W + w] = v[k1];
+    for (int k1 = 0; k1 < N1; ++k1) E[k1 * ES + p * EP] = v[k1];
+    __syncthreads();
+    C2<float> u[C][N2];
+#pragma unroll
+    for (int s2 = 0; s2 < C; ++s2)
+#pragma unroll
+        for (int j2 = 0; j2 < N2; ++j2) u[s2][j2] = E[(p + N2 * s2) * ES + j2 * EP];
     __syncthreads();
 #pragma unroll
-    for (int j2 = 0; j2 < N2; ++j2) v[j2] = E[p * G::PL + j2 * W + w];
-    __syncthreads();
-    RDFT<float, N2, DIR>::run(v);
+    for (int s2 = 0; s2 < C; ++s2) RDFT<float, N2, DIR>::run(u[s2]);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) v[i] = u[i % C][i / C];
 }
 
-// thread (w, p): v[k2] = X[p + N1 k2]  ->  v[b] = x[p + N2 b] (inverse, unnormalised)
+// y and z passes: W adjacent kx columns per workgroup, N2 threads per column
 template <int N1, int N2, int W>
-__device__ inline void reg_fft_inv_spec(C2<float>* v, const C2<float>* tw, C2<float>* E, int w,
-                                        int p) {
-    using G = RegGeom<N1, N2, W>;
-    RDFT<float, N2, 1>::run(v);
-#pragma unroll
-    for (int a = 1; a < N2; ++a) {
-        C2<float> t = tw[p * a];
-        t.y = -t.y;
-        v[a] = cmul(v[a], t);
-    }
-#pragma unroll
-    for (int a = 0; a < N2; ++a) E[a * G::PL + p * W + w] = v[a];
-    __syncthreads();
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) v[k1] = E[p * G::PL + k1 * W + w];
-    __syncthreads();
-    RDFT<float, N1, 1>::run(v);
-}
+struct ColGeom {
+    static constexpr int M = N1 * N2;
+    static constexpr int H = M / 2;
+    static constexpr int NT = W * N2;        // threads per block
+    static constexpr int PL = N2 * W + 8;    // exchange-buffer stride of k1 (complex)
+    static constexpr int NG = H / W;         // column groups per kx row
+    static_assert(H % W == 0, "W must divide M/2");
+    static_assert(NT <= 256, "block size");
+};
 
-// y pass (register form): one (component, z) plane and W kx columns per block
+// y pass: one (component, z) plane and W kx columns per block
 template <int N1, int N2, int W, int DIR>
-__global__ __launch_bounds__(W * N2) void k_fft_y_reg(
-    C2<float>* __restrict__ spec, const C2<float>* __restrict__ twg) {
-    using G = RegGeom<N1, N2, W>;
+__global__ __launch_bounds__(W * N2) void k_fft_y_reg(C2<float>* __restrict__ spec,
+                                                      const C2<float>* __restrict__ twg) {
+    using G = ColGeom<N1, N2, W>;
     __shared__ C2<float> tw[G::M];
     __shared__ C2<float> E[N1 * G::PL];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -545,19 +536,20 @@ __global__ __launch_bounds__(W * N2) void k_fft_y_reg(
     for (int e = threadIdx.x; e < G::M; e += G::NT) tw[e] = twg[e];
     C2<float> v[N1];
 #pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) v[j1] = at(lo + j1 * N2 * G::H * 8u);
+    for (int j = 0; j < N1; ++j) v[j] = at(lo + j * N2 * G::H * 8u);
     __syncthreads();
-    reg_fft_fwd<N1, N2, W, DIR>(v, tw, E, w, p);
+    four_step<N1, N2, DIR, 1>(v, tw, E + w, p, G::PL, W);
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) at(lo + N1 * k2 * G::H * 8u) = v[k2];
+    for (int i = 0; i < N1; ++i) at(lo + i * N2 * G::H * 8u) = v[i];
 }
 
-// z pass (register form): forward FFT along z of the three components of W kx
-// columns at one ky, the projection, and the inverse FFT along z
+// z pass: forward FFT along z of the three components of W kx columns at one
+// ky, the projection, and the inverse FFT along z
 template <int N1, int N2, int W>
-__global__ __launch_bounds__(W * N2) void k_fft_z_solve_reg(
-    C2<float>* __restrict__ spec, const C2<float>* __restrict__ twg, ProjArgs pa) {
-    using G = RegGeom<N1, N2, W>;
+__global__ __launch_bounds__(W * N2) void k_fft_z_solve_reg(C2<float>* __restrict__ spec,
+                                                            const C2<float>* __restrict__ twg,
+                                                            ProjArgs pa) {
+    using G = ColGeom<N1, N2, W>;
     constexpr int M = G::M, H = G::H;
     __shared__ C2<float> tw[M];
     __shared__ C2<float> E[N1 * G::PL];
@@ -577,91 +569,93 @@ __global__ __launch_bounds__(W * N2) void k_fft_z_solve_reg(
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int j1 = 0; j1 < N1; ++j1) v[c][j1] = buf_load(rs, lo, c * cstride + j1 * N2 * zstride);
+        for (int j = 0; j < N1; ++j) v[c][j] = buf_load(rs, lo, c * cstride + j * N2 * zstride);
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 3; ++c) reg_fft_fwd<N1, N2, W, -1>(v[c], tw, E, w, p);
+    for (int c = 0; c < 3; ++c) four_step<N1, N2, -1, 1>(v[c], tw, E + w, p, G::PL, W);
     // projection: u^ = (I - k k^T / k^2) f^ / (eta k^2 M^3); k = 0 and index-H modes -> 0
     const float ku = (float)pa.kunit, sc = (float)pa.scale;
     const int jx = g * W + w;
     const int jy = y < H ? y : y - M;
     const float kx = ku * (float)jx, ky = ku * (float)jy;
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) {
-        const int iz = p + N1 * k2;
+    for (int i = 0; i < N1; ++i) {
+        const int iz = p + N2 * i;
         const int jz = iz < H ? iz : iz - M;
         const bool zero = (y == H) || (iz == H) || (jx == 0 && jy == 0 && jz == 0);
         const float kz = ku * (float)jz;
         const float k2s = kx * kx + ky * ky + kz * kz;
         const float ik2 = zero ? 0.0f : 1.0f / k2s;
-        const C2<float> f0 = v[0][k2], f1 = v[1][k2], f2 = v[2][k2];
+        const C2<float> f0 = v[0][i], f1 = v[1][i], f2 = v[2][i];
         const C2<float> kf = {(kx * f0.x + ky * f1.x + kz * f2.x) * ik2,
                               (kx * f0.y + ky * f1.y + kz * f2.y) * ik2};
         const float s = sc * ik2;
-        v[0][k2] = C2<float>{(f0.x - kx * kf.x) * s, (f0.y - kx * kf.y) * s};
-        v[1][k2] = C2<float>{(f1.x - ky * kf.x) * s, (f1.y - ky * kf.y) * s};
-        v[2][k2] = C2<float>{(f2.x - kz * kf.x) * s, (f2.y - kz * kf.y) * s};
+        v[0][i] = C2<float>{(f0.x - kx * kf.x) * s, (f0.y - kx * kf.y) * s};
+        v[1][i] = C2<float>{(f1.x - ky * kf.x) * s, (f1.y - ky * kf.y) * s};
+        v[2][i] = C2<float>{(f2.x - kz * kf.x) * s, (f2.y - kz * kf.y) * s};
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) reg_fft_inv_spec<N1, N2, W>(v[c], tw, E, w, p);
+    for (int c = 0; c < 3; ++c) four_step<N1, N2, 1, 1>(v[c], tw, E + w, p, G::PL, W);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int b = 0; b < N1; ++b) buf_store(v[c][b], rs, lo, c * cstride + N2 * b * zstride);
+        for (int i = 0; i < N1; ++i) buf_store(v[c][i], rs, lo, c * cstride + i * N2 * zstride);
 }
 
-// x passes (register form) for a half-length H = N1 N2 with N1 = 2 N2:
-// T = N2 threads per line, each holding the N1 complex values of index
-// congruent to its lane q modulo T.  Step 1 is an N1-point DFT per thread,
-// step 2 two N2-point DFTs per thread after one LDS exchange; the result
-// X[q + T i] lands back in the same lane-modulo-T layout, so the real/complex
-// split, which pairs index k with H - k, only needs lane shuffles: the
-// partner of (q, i) is lane T - q, register N1 - 1 - i (lane 0: itself,
-// register (N1 - i) mod N1).
+// x passes for a half-length H = N1 N2: T = N2 threads per line hold the
+// values of index congruent to their lane q modulo T, before and after the
+// transform.  The real/complex split pairs index k with H - k, whose holder
+// is lane T - q, register N1 - 1 - i (lane 0: itself, register (N1 - i) mod
+// N1): exchanged by lane shuffles when T is a power of two dividing 64 (a
+// line's lanes then share a wavefront), through LDS otherwise.
 template <int N1, int N2>
 struct XGeom {
-    static_assert(N1 == 2 * N2, "N1 = 2 N2");
     static constexpr int H = N1 * N2, M = 2 * H, T = N2;
-    static constexpr int NT = 256, LPB = NT / T;   // threads, lines per block
-    static constexpr int KS = N2 + 1;              // exchange: k1 stride (complex)
-    static constexpr int LS = 168;                 // exchange: line stride (complex)
-    static_assert(N1 * KS <= LS, "line stride");
+    static constexpr int KS = N2 + 1;               // exchange: k1 stride (complex)
+    static constexpr int LS = (N1 * KS + 31) / 32 * 32 + 8;   // exchange: line stride
+    // lines per block: a multiple of 4, at most 32, exchange buffer within 56 KiB
+    static constexpr int lpb(int l) { return (l > 4 && l * LS * 8 > 57344) ? lpb(l - 4) : l; }
+    static constexpr int LPB = lpb((256 / T) / 4 * 4 > 32 ? 32 : (256 / T) / 4 * 4);
+    static constexpr int NT = LPB * T;
+    static constexpr bool SHFL = (T & (T - 1)) == 0 && 64 % T == 0;
+    static_assert(LS >= H, "line buffer holds a line");
 };
-
-template <int N1, int N2, int DIR>
-__device__ inline void xfft_two_step(C2<float>* v, const C2<float>* tw, C2<float>* E, int q) {
-    using G = XGeom<N1, N2>;
-    // v[j1] = z[j1 T + q]
-    RDFT<float, N1, DIR>::run(v);
-#pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) {
-        C2<float> t = tw[2 * q * k1];   // exp(-2 pi i q k1 / H)
-        if (DIR > 0) t.y = -t.y;
-        v[k1] = cmul(v[k1], t);
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) E[k1 * G::KS + q] = v[k1];
-    __syncthreads();
-    C2<float> u[2][N2];
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-        for (int j2 = 0; j2 < N2; ++j2) u[s2][j2] = E[(q + G::T * s2) * G::KS + j2];
-    __syncthreads();
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) RDFT<float, N2, DIR>::run(u[s2]);
-    // X[k1 + N1 k2] with k1 = q + T s2  ->  X[q + T i], i = s2 + 2 k2
-#pragma unroll
-    for (int i = 0; i < N1; ++i) v[i] = u[i & 1][i >> 1];
-}
 
 __device__ inline C2<float> shfl_c(C2<float> v, int src) {
     return C2<float>{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
 }
 
+// the values at H - k of a line held in the lane-modulo-T layout (index 0's
+// partner, X_H, is returned as X_0; the callers treat it)
 template <int N1, int N2>
-__global__ __launch_bounds__(256) void k_fft_x_r2c_reg(float* __restrict__ grid,
-                                                       const C2<float>* __restrict__ twg, int nlines) {
+__device__ inline void x_partners(const C2<float>* v, C2<float>* pv, C2<float>* Eline, int q) {
+    using G = XGeom<N1, N2>;
+    constexpr int T = G::T;
+    if constexpr (G::SHFL) {
+        const int lane = threadIdx.x & 63;
+        const int partner = (lane & ~(T - 1)) | ((T - q) & (T - 1));
+#pragma unroll
+        for (int i = 0; i < N1; ++i) {
+            const C2<float> a = shfl_c(v[N1 - 1 - i], partner);
+            pv[i] = (q == 0) ? v[(N1 - i) % N1] : a;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N1; ++i) Eline[q + T * i] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < N1; ++i) {
+            const int k = q + T * i;
+            pv[i] = Eline[k == 0 ? 0 : G::H - k];
+        }
+        __syncthreads();
+    }
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__((XGeom<N1, N2>::NT)) void k_fft_x_r2c_reg(float* __restrict__ grid,
+                                                                     const C2<float>* __restrict__ twg,
+                                                                     int nlines) {
     using G = XGeom<N1, N2>;
     constexpr int H = G::H, T = G::T;
     __shared__ C2<float> tw[G::M];
@@ -673,16 +667,15 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c_reg(float* __restrict__ grid,
     for (int e = tid; e < G::M; e += G::NT) tw[e] = twg[e];
     C2<float> v[N1];
 #pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) v[j1] = ok ? g[j1 * T + q] : C2<float>{0, 0};
+    for (int j = 0; j < N1; ++j) v[j] = ok ? g[j * T + q] : C2<float>{0, 0};
     __syncthreads();
-    xfft_two_step<N1, N2, -1>(v, tw, E + ll * G::LS, q);
+    four_step<N1, N2, -1, 2>(v, tw, E + ll * G::LS, q, G::KS, 1);
     // split: X_k = (Z_k + conj Z_{H-k})/2 - (i/2) exp(-2 pi i k/M) (Z_k - conj Z_{H-k})
-    const int lane = threadIdx.x & 63;
-    const int partner = (lane & ~(T - 1)) | ((T - q) & (T - 1));
+    C2<float> pv[N1];
+    x_partners<N1, N2>(v, pv, E + ll * G::LS, q);
 #pragma unroll
     for (int i = 0; i < N1; ++i) {
-        const C2<float> a = shfl_c(v[N1 - 1 - i], partner);
-        C2<float> Zc = (q == 0) ? v[(N1 - i) % N1] : a;
+        C2<float> Zc = pv[i];
         Zc.y = -Zc.y;
         const int k = q + T * i;
         const C2<float> S = cadd(v[i], Zc), D = csub(v[i], Zc);
@@ -692,8 +685,9 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c_reg(float* __restrict__ grid,
 }
 
 template <int N1, int N2, bool TILED>
-__global__ __launch_bounds__(256) void k_fft_x_c2r_reg(float* __restrict__ grid,
-                                                       const C2<float>* __restrict__ twg, int nlines) {
+__global__ __launch_bounds__((XGeom<N1, N2>::NT)) void k_fft_x_c2r_reg(float* __restrict__ grid,
+                                                                     const C2<float>* __restrict__ twg,
+                                                                     int nlines) {
     using G = XGeom<N1, N2>;
     constexpr int H = G::H, T = G::T;
     __shared__ C2<float> tw[G::M];
@@ -709,24 +703,23 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r_reg(float* __restrict__ grid,
     __syncthreads();
     // Z_k = E + i O, E = X_k + conj X_{H-k}, O = exp(+2 pi i k/M) (X_k - conj X_{H-k}),
     // with the x-Nyquist coefficient X_H taken as 0
-    const int lane = threadIdx.x & 63;
-    const int partner = (lane & ~(T - 1)) | ((T - q) & (T - 1));
+    C2<float> pv[N1];
+    x_partners<N1, N2>(x, pv, E + ll * G::LS, q);
     C2<float> z[N1];
 #pragma unroll
     for (int i = 0; i < N1; ++i) {
-        const C2<float> a = shfl_c(x[N1 - 1 - i], partner);
-        C2<float> Xc = (q == 0) ? (i == 0 ? C2<float>{0, 0} : x[(N1 - i) % N1]) : a;
-        Xc.y = -Xc.y;
         const int k = q + T * i;
+        C2<float> Xc = (k == 0) ? C2<float>{0, 0} : pv[i];
+        Xc.y = -Xc.y;
         const C2<float> Ev = cadd(x[i], Xc);
         C2<float> wk = tw[k];
         wk.y = -wk.y;
         const C2<float> O = cmul(csub(x[i], Xc), wk);
         z[i] = C2<float>{Ev.x - O.y, Ev.y + O.x};
     }
-    xfft_two_step<N1, N2, 1>(z, tw, E + ll * G::LS, q);
+    four_step<N1, N2, 1, 2>(z, tw, E + ll * G::LS, q, G::KS, 1);
     if (TILED) {
-        // tiles of 8 x by 4 y: a block's lines are 32 consecutive y of one plane
+        // tiles of 8 x by 4 y; a block's lines are groups of 4 consecutive y
         constexpr int M = G::M;
         const int y = line % M;
         float* pl = grid + (size_t)(line / M) * M * M + (size_t)(y >> 2) * (M << 2) + ((y & 3) << 3);
@@ -742,8 +735,102 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r_reg(float* __restrict__ grid,
     }
 }
 
+
+// the z pass in LDS (all sizes and precisions)
+template <typename R, int MZ>
+void z_lds(const fcm_plan_impl* P, C2<R>* spec, const C2<R>* tw, hipStream_t st, ProjArgs pa) {
+    const int M = P->M, H = P->H;
+    const int ngz = (H + P->Wz - 1) / P->Wz;
+    const size_t shz = (M + 3 * (size_t)P->Wz * M) * sizeof(C2<R>);
+    hipLaunchKernelGGL((k_fft_z_solve<R, MZ>), dim3(ngz * M), dim3(kFFTThreads), shz, st, spec, tw,
+                       M, P->radM, P->Wz, __builtin_ctz(P->Wz), pa);
+}
+
+ProjArgs proj_args(const fcm_plan_impl* P) {
+    ProjArgs pa;
+    pa.kunit = 2.0 * 3.14159265358979323846 / P->L;
+    pa.scale = 1.0 / (P->eta * (double)P->M * P->M * P->M);
+    return pa;
+}
+
+// FP32 solve with register passes (RegPlan sizes)
+template <int XN1, int XN2, int YN1, int YN2, int YW, bool ZREG>
+hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEvent_t* ev, bool tiled) {
+    using X = XGeom<XN1, XN2>;
+    using Y = ColGeom<YN1, YN2, YW>;
+    static_assert(2 * X::H == Y::M, "x and y factorisations of the same M");
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    constexpr int M = Y::M;
+    const C2<float>* tw = (const C2<float>*)P->twid;
+    C2<float>* spec = (C2<float>*)grid;
+    const int nlines = 3 * M * M;
+    const dim3 gx((nlines + X::LPB - 1) / X::LPB), bx(X::NT);
+    mark(0);
+    hipLaunchKernelGGL((k_fft_x_r2c_reg<XN1, XN2>), gx, bx, 0, st, grid, tw, nlines);
+    mark(1);
+    hipLaunchKernelGGL((k_fft_y_reg<YN1, YN2, YW, -1>), dim3(Y::NG * 3 * M), dim3(Y::NT), 0, st, spec,
+                       tw);
+    mark(2);
+    if constexpr (ZREG)
+        hipLaunchKernelGGL((k_fft_z_solve_reg<YN1, YN2, YW>), dim3(Y::NG * M), dim3(Y::NT), 0, st, spec,
+                           tw, proj_args(P));
+    else
+        z_lds<float, 8>(P, spec, tw, st, proj_args(P));
+    mark(3);
+    hipLaunchKernelGGL((k_fft_y_reg<YN1, YN2, YW, 1>), dim3(Y::NG * 3 * M), dim3(Y::NT), 0, st, spec,
+                       tw);
+    mark(4);
+    if (tiled && M % 8 == 0)
+        hipLaunchKernelGGL((k_fft_x_c2r_reg<XN1, XN2, true>), gx, bx, 0, st, grid, tw, nlines);
+    else
+        hipLaunchKernelGGL((k_fft_x_c2r_reg<XN1, XN2, false>), gx, bx, 0, st, grid, tw, nlines);
+    mark(5);
+    return hipGetLastError();
+}
+
+// The sizes with register passes: M -> (x: M/2 = XN1 XN2), (y, z: M = YN1 YN2 over
+// YW columns), whether the z pass fits in registers.
+#define FCM_REG_SIZES(X)                   \
+    X(64, 8, 4, 8, 8, 32, true)            \
+    X(72, 18, 2, 12, 6, 36, true)          \
+    X(96, 12, 4, 24, 4, 48, false)         \
+    X(108, 18, 3, 18, 6, 27, true)         \
+    X(128, 8, 8, 16, 8, 32, true)          \
+    X(144, 12, 6, 12, 12, 18, true)        \
+    X(162, 9, 9, 18, 9, 27, true)          \
+    X(192, 24, 4, 24, 8, 32, false)        \
+    X(216, 18, 6, 36, 6, 18, false)        \
+    X(256, 16, 8, 16, 16, 16, true)        \
+    X(288, 12, 12, 24, 12, 16, false)      \
+    X(324, 18, 9, 18, 18, 9, true)         \
+    X(384, 24, 8, 48, 8, 16, false)        \
+    X(432, 36, 6, 36, 12, 12, false)
+
+bool reg_size(int M) {
+#define FCM_REG_CASE(m, a, b, c, d, e, f) \
+    case m:                               \
+        return true;
+    switch (M) {
+        FCM_REG_SIZES(FCM_REG_CASE)
+        default: return false;
+    }
+#undef FCM_REG_CASE
+}
+
 template <typename R, int MX, int MZ>
 hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* ev, bool tiled) {
+    if constexpr (sizeof(R) == sizeof(float)) {
+#define FCM_REG_CASE(m, a, b, c, d, e, f) \
+    case m:                               \
+        return solve_reg<a, b, c, d, e, f>(P, grid, st, ev, tiled);
+        switch (P->M) {
+            FCM_REG_SIZES(FCM_REG_CASE)
+            default: break;
+        }
+#undef FCM_REG_CASE
+    }
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
@@ -752,15 +839,8 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
     C2<R>* spec = (C2<R>*)grid;
     const int nlines = 3 * M * M;
     const size_t cs = sizeof(C2<R>);
-    ProjArgs pa;
-    pa.kunit = 2.0 * 3.14159265358979323846 / P->L;
-    pa.scale = 1.0 / (P->eta * (double)M * M * M);
     mark(0);
-    if (sizeof(R) == sizeof(float) && M == 256) {
-        using G = XGeom<16, 8>;
-        hipLaunchKernelGGL((k_fft_x_r2c_reg<16, 8>), dim3((nlines + G::LPB - 1) / G::LPB), dim3(G::NT),
-                           0, st, (float*)grid, (const C2<float>*)tw, nlines);
-    } else {
+    {
         const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;
         hipLaunchKernelGGL((k_fft_x_r2c<R, MX>), dim3((nlines + P->Wx - 1) / P->Wx),
                            dim3(kFFTThreads), shm, st, grid, tw, M, P->radH, P->Wx, nlines);
@@ -768,47 +848,16 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
     mark(1);
     const int ngy = (H + P->Wy - 1) / P->Wy;
     const size_t shy = (M + (size_t)P->Wy * M) * cs;
-    const int lwy = __builtin_ctz(P->Wy), lwz = __builtin_ctz(P->Wz);
-    if constexpr (sizeof(R) == sizeof(float)) {
-        if (M == 256) {
-            using G = RegGeom<16, 16, 16>;
-            C2<float>* sp = (C2<float>*)spec;
-            const C2<float>* tf = (const C2<float>*)tw;
-            hipLaunchKernelGGL((k_fft_y_reg<16, 16, 16, -1>), dim3(G::NG * 3 * M), dim3(G::NT), 0, st,
-                               sp, tf);
-            mark(2);
-            hipLaunchKernelGGL((k_fft_z_solve_reg<16, 16, 16>), dim3(G::NG * M), dim3(G::NT), 0, st, sp,
-                               tf, pa);
-            mark(3);
-            hipLaunchKernelGGL((k_fft_y_reg<16, 16, 16, 1>), dim3(G::NG * 3 * M), dim3(G::NT), 0, st,
-                               sp, tf);
-            mark(4);
-        }
-    }
-    if (sizeof(R) != sizeof(float) || M != 256) {
-        hipLaunchKernelGGL((k_fft_y<R, -1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec,
-                           tw, M, P->radM, P->Wy, lwy);
-        mark(2);
-        {
-            const int ngz = (H + P->Wz - 1) / P->Wz;
-            const size_t shz = (M + 3 * (size_t)P->Wz * M) * cs;
-            hipLaunchKernelGGL((k_fft_z_solve<R, MZ>), dim3(ngz * M), dim3(kFFTThreads), shz, st,
-                               spec, tw, M, P->radM, P->Wz, lwz, pa);
-        }
-        mark(3);
-        hipLaunchKernelGGL((k_fft_y<R, 1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec,
-                           tw, M, P->radM, P->Wy, lwy);
-        mark(4);
-    }
-    if (sizeof(R) == sizeof(float) && M == 256) {
-        using G = XGeom<16, 8>;
-        if (tiled)
-            hipLaunchKernelGGL((k_fft_x_c2r_reg<16, 8, true>), dim3((nlines + G::LPB - 1) / G::LPB),
-                               dim3(G::NT), 0, st, (float*)grid, (const C2<float>*)tw, nlines);
-        else
-            hipLaunchKernelGGL((k_fft_x_c2r_reg<16, 8, false>), dim3((nlines + G::LPB - 1) / G::LPB),
-                               dim3(G::NT), 0, st, (float*)grid, (const C2<float>*)tw, nlines);
-    } else {
+    const int lwy = __builtin_ctz(P->Wy);
+    hipLaunchKernelGGL((k_fft_y<R, -1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec, tw,
+                       M, P->radM, P->Wy, lwy);
+    mark(2);
+    z_lds<R, MZ>(P, spec, tw, st, proj_args(P));
+    mark(3);
+    hipLaunchKernelGGL((k_fft_y<R, 1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec, tw, M,
+                       P->radM, P->Wy, lwy);
+    mark(4);
+    {
         const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;
         hipLaunchKernelGGL((k_fft_x_c2r<R, MX>), dim3((nlines + P->Wx - 1) / P->Wx),
                            dim3(kFFTThreads), shm, st, grid, tw, M, P->radH, P->Wx, nlines);
@@ -825,7 +874,9 @@ int fft_maxe(int precision, bool zpass) {
     return zpass ? 8 : 16;
 }
 
-bool solve_tiles(const fcm_plan_impl* P) { return P->precision != FCM_FP64 && P->M == 256; }
+bool solve_tiles(const fcm_plan_impl* P) {
+    return P->precision != FCM_FP64 && reg_size(P->M) && P->M % 8 == 0;
+}
 
 hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st, hipEvent_t* ev,
                         bool tiled) {
