@@ -446,10 +446,10 @@ int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double*
     if (e == hipSuccess)
         e = corr ? launch_gather_both(p, pos, F, T, st) : launch_gather_grid(p, pos, F, T, st);
     mark(1);
-    if (e == hipSuccess) e = launch_spread(p, T != nullptr, p->grid, st);
-    // the field stays inside the call, so the solve may hand it to the
-    // interpolation in the tiled layout
+    // the field stays inside the call, so spread, solve and interpolation may
+    // pass it along in the tiled layout
     const bool tiled = solve_tiles(p);
+    if (e == hipSuccess) e = launch_spread(p, T != nullptr, p->grid, st, tiled);
     if (e == hipSuccess) e = launch_solve(p, p->grid, st, ev ? ev + 2 : nullptr, tiled);
     if (e == hipSuccess) e = launch_interp(p, p->grid, V, Omega, st, tiled);
     mark(8);

@@ -652,7 +652,7 @@ __device__ inline void x_partners(const C2<float>* v, C2<float>* pv, C2<float>* 
     }
 }
 
-template <int N1, int N2>
+template <int N1, int N2, bool TILED>
 __global__ __launch_bounds__((XGeom<N1, N2>::NT)) void k_fft_x_r2c_reg(float* __restrict__ grid,
                                                                      const C2<float>* __restrict__ twg,
                                                                      int nlines) {
@@ -666,8 +666,23 @@ __global__ __launch_bounds__((XGeom<N1, N2>::NT)) void k_fft_x_r2c_reg(float* __
     C2<float>* g = reinterpret_cast<C2<float>*>(grid) + (size_t)(ok ? line : 0) * H;
     for (int e = tid; e < G::M; e += G::NT) tw[e] = twg[e];
     C2<float> v[N1];
+    if (TILED) {
+        // tiles of 8 x by 4 y (as written by the spread); a block's lines are
+        // groups of 4 consecutive y
+        constexpr int M = G::M;
+        const int y = line % M;
+        const float* pl =
+            grid + (size_t)(line / M) * M * M + (size_t)(y >> 2) * (M << 2) + ((y & 3) << 3);
 #pragma unroll
-    for (int j = 0; j < N1; ++j) v[j] = ok ? g[j * T + q] : C2<float>{0, 0};
+        for (int j = 0; j < N1; ++j) {
+            const int x = 2 * (j * T + q);
+            v[j] = ok ? *reinterpret_cast<const C2<float>*>(pl + ((x >> 3) << 5) + (x & 7))
+                      : C2<float>{0, 0};
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < N1; ++j) v[j] = ok ? g[j * T + q] : C2<float>{0, 0};
+    }
     __syncthreads();
     four_step<N1, N2, -1, 2>(v, tw, E + ll * G::LS, q, G::KS, 1);
     // split: X_k = (Z_k + conj Z_{H-k})/2 - (i/2) exp(-2 pi i k/M) (Z_k - conj Z_{H-k})
@@ -767,8 +782,12 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     C2<float>* spec = (C2<float>*)grid;
     const int nlines = 3 * M * M;
     const dim3 gx((nlines + X::LPB - 1) / X::LPB), bx(X::NT);
+    const bool tl = tiled && M % 8 == 0;
     mark(0);
-    hipLaunchKernelGGL((k_fft_x_r2c_reg<XN1, XN2>), gx, bx, 0, st, grid, tw, nlines);
+    if (tl)
+        hipLaunchKernelGGL((k_fft_x_r2c_reg<XN1, XN2, true>), gx, bx, 0, st, grid, tw, nlines);
+    else
+        hipLaunchKernelGGL((k_fft_x_r2c_reg<XN1, XN2, false>), gx, bx, 0, st, grid, tw, nlines);
     mark(1);
     hipLaunchKernelGGL((k_fft_y_reg<YN1, YN2, YW, -1>), dim3(Y::NG * 3 * M), dim3(Y::NT), 0, st, spec,
                        tw);
@@ -782,7 +801,7 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     hipLaunchKernelGGL((k_fft_y_reg<YN1, YN2, YW, 1>), dim3(Y::NG * 3 * M), dim3(Y::NT), 0, st, spec,
                        tw);
     mark(4);
-    if (tiled && M % 8 == 0)
+    if (tl)
         hipLaunchKernelGGL((k_fft_x_c2r_reg<XN1, XN2, true>), gx, bx, 0, st, grid, tw, nlines);
     else
         hipLaunchKernelGGL((k_fft_x_c2r_reg<XN1, XN2, false>), gx, bx, 0, st, grid, tw, nlines);
@@ -795,15 +814,15 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
 #define FCM_REG_SIZES(X)                   \
     X(64, 8, 4, 8, 8, 32, true)            \
     X(72, 18, 2, 12, 6, 36, true)          \
-    X(96, 12, 4, 24, 4, 48, false)         \
+    X(96, 12, 4, 24, 4, 48, true)          \
     X(108, 18, 3, 18, 6, 27, true)         \
     X(128, 8, 8, 16, 8, 32, true)          \
     X(144, 12, 6, 12, 12, 18, true)        \
     X(162, 9, 9, 18, 9, 27, true)          \
-    X(192, 24, 4, 24, 8, 32, false)        \
+    X(192, 24, 4, 24, 8, 32, true)         \
     X(216, 18, 6, 36, 6, 18, false)        \
     X(256, 16, 8, 16, 16, 16, true)        \
-    X(288, 12, 12, 24, 12, 16, false)      \
+    X(288, 12, 12, 24, 12, 16, true)       \
     X(324, 18, 9, 18, 18, 9, true)         \
     X(384, 24, 8, 48, 8, 16, false)        \
     X(432, 36, 6, 36, 12, 12, false)

@@ -115,20 +115,50 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
     // The bins that can reach the tile are bx in btx-backx .. btx (mod nbx)
     // for each (by, bz) row; bins are numbered x fastest and particles are
     // sorted by bin, so each row is one contiguous run of particles (two when
-    // it wraps around the periodic x boundary).
-    for (int oz = 0; oz <= a.backz; ++oz) {
+    // it wraps around the periodic x boundary).  One lane per row fetches the
+    // row's bounds, so all of them arrive in one round trip.
+    __shared__ int4 runs[64];
+    const int nrows = (a.backy + 1) * (a.backz + 1);
+    for (int rr = lane; rr < nrows; rr += 64) {
+        const int oz = rr / (a.backy + 1), oy = rr - oz * (a.backy + 1);
         int bz = btz - oz;
         if (bz < 0) bz += a.nbz;
-        for (int oy = 0; oy <= a.backy; ++oy) {
-            int by = bty - oy;
-            if (by < 0) by += a.nby;
-            const int row = a.nbx * (by + a.nby * bz);
-            const int bx0 = btx - a.backx;
-            const bool wraps = bx0 < 0;
-            const int beg0 = bin_start[row + (wraps ? bx0 + a.nbx : bx0)];
-            const int end0 = bin_start[row + (wraps ? a.nbx : btx + 1)];
-            const int beg1 = wraps ? bin_start[row] : 0;
-            const int end1 = wraps ? bin_start[row + btx + 1] : 0;
+        int by = bty - oy;
+        if (by < 0) by += a.nby;
+        const int row = a.nbx * (by + a.nby * bz);
+        const int bx0 = btx - a.backx;
+        const bool wraps = bx0 < 0;
+        int4 b;
+        b.x = bin_start[row + (wraps ? bx0 + a.nbx : bx0)];
+        b.y = bin_start[row + (wraps ? a.nbx : btx + 1)];
+        b.z = wraps ? bin_start[row] : 0;
+        b.w = wraps ? bin_start[row + btx + 1] : 0;
+        if (rr < 64) runs[rr] = b;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < nrows; ++rr) {
+        {
+            int4 b;
+            if (rr < 64) {
+                b = runs[rr];
+            } else {
+                const int oz = rr / (a.backy + 1), oy = rr - oz * (a.backy + 1);
+                int bz = btz - oz;
+                if (bz < 0) bz += a.nbz;
+                int by = bty - oy;
+                if (by < 0) by += a.nby;
+                const int row = a.nbx * (by + a.nby * bz);
+                const int bx0 = btx - a.backx;
+                const bool wraps = bx0 < 0;
+                b.x = bin_start[row + (wraps ? bx0 + a.nbx : bx0)];
+                b.y = bin_start[row + (wraps ? a.nbx : btx + 1)];
+                b.z = wraps ? bin_start[row] : 0;
+                b.w = wraps ? bin_start[row + btx + 1] : 0;
+            }
+            const int beg0 = __builtin_amdgcn_readfirstlane(b.x);
+            const int end0 = __builtin_amdgcn_readfirstlane(b.y);
+            const int beg1 = __builtin_amdgcn_readfirstlane(b.z);
+            const int end1 = __builtin_amdgcn_readfirstlane(b.w);
             for (int run = 0; run < 2; ++run) {
                 const int beg = run ? beg1 : beg0, end = run ? end1 : end0;
                 for (int base = beg; base < end; base += kChunk) {
@@ -267,9 +297,12 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
     }
     if (lact) {
         const size_t M3 = (size_t)M * M * M;
+        const size_t col = a.tiled ? (size_t)((gyp >> 2) * (M << 2) + ((gxp >> 3) << 5) + ((gyp & 3) << 3) +
+                                              (gxp & 7))
+                                   : (size_t)gyp * M + gxp;
 #pragma unroll
         for (int k = 0; k < TZ; ++k) {
-            const size_t idx = ((size_t)(Z0 + k) * M + gyp) * M + gxp;
+            const size_t idx = (size_t)(Z0 + k) * M * M + col;
 #pragma unroll
             for (int c = 0; c < 3; ++c) grid[c * M3 + idx] = acc[c][k].value();
         }
@@ -589,8 +622,9 @@ GridArgs<R> make_args(const fcm_plan_impl* P) {
 }
 
 template <typename R, int TZ, int MODE, bool TORQUE>
-hipError_t spread_tz(const fcm_plan_impl* P, R* grid, hipStream_t st) {
+hipError_t spread_tz(const fcm_plan_impl* P, R* grid, hipStream_t st, bool tiled) {
     GridArgs<R> a = make_args<R>(P);
+    a.tiled = tiled ? 1 : 0;
     const size_t shm = sizeof(Stage<R>) + kChunk * (size_t)P->MG * sizeof(ZTab<R>);
     dim3 g(P->nbins), b(64);
     const GridRec<R>* rec = (const GridRec<R>*)P->grec;
@@ -602,22 +636,23 @@ hipError_t spread_tz(const fcm_plan_impl* P, R* grid, hipStream_t st) {
 }
 
 template <typename R, int MODE, bool TORQUE>
-hipError_t spread_m(const fcm_plan_impl* P, R* grid, hipStream_t st) {
+hipError_t spread_m(const fcm_plan_impl* P, R* grid, hipStream_t st, bool tiled) {
     switch (P->TZ) {
-        case 16: return spread_tz<R, 16, MODE, TORQUE>(P, grid, st);
-        case 12: return spread_tz<R, 12, MODE, TORQUE>(P, grid, st);
-        case 8: return spread_tz<R, 8, MODE, TORQUE>(P, grid, st);
-        case 6: return spread_tz<R, 6, MODE, TORQUE>(P, grid, st);
-        case 4: return spread_tz<R, 4, MODE, TORQUE>(P, grid, st);
-        case 2: return spread_tz<R, 2, MODE, TORQUE>(P, grid, st);
-        case 1: return spread_tz<R, 1, MODE, TORQUE>(P, grid, st);
+        case 16: return spread_tz<R, 16, MODE, TORQUE>(P, grid, st, tiled);
+        case 12: return spread_tz<R, 12, MODE, TORQUE>(P, grid, st, tiled);
+        case 8: return spread_tz<R, 8, MODE, TORQUE>(P, grid, st, tiled);
+        case 6: return spread_tz<R, 6, MODE, TORQUE>(P, grid, st, tiled);
+        case 4: return spread_tz<R, 4, MODE, TORQUE>(P, grid, st, tiled);
+        case 2: return spread_tz<R, 2, MODE, TORQUE>(P, grid, st, tiled);
+        case 1: return spread_tz<R, 1, MODE, TORQUE>(P, grid, st, tiled);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename R, int MODE>
-hipError_t spread_r(const fcm_plan_impl* P, bool torque, R* grid, hipStream_t st) {
-    return torque ? spread_m<R, MODE, true>(P, grid, st) : spread_m<R, MODE, false>(P, grid, st);
+hipError_t spread_r(const fcm_plan_impl* P, bool torque, R* grid, hipStream_t st, bool tiled) {
+    return torque ? spread_m<R, MODE, true>(P, grid, st, tiled)
+                  : spread_m<R, MODE, false>(P, grid, st, tiled);
 }
 
 template <typename R>
@@ -652,11 +687,13 @@ hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W,
 
 }  // namespace
 
-hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st) {
-    if (P->precision == FCM_FP64) return spread_r<double, ACC_PLAIN>(P, torque, (double*)grid, st);
-    if (P->kahan == 1) return spread_r<float, ACC_KAHAN>(P, torque, (float*)grid, st);
-    if (P->kahan == 2) return spread_r<float, ACC_WIDE>(P, torque, (float*)grid, st);
-    return spread_r<float, ACC_PLAIN>(P, torque, (float*)grid, st);
+hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st,
+                         bool tiled) {
+    if (P->precision == FCM_FP64)
+        return spread_r<double, ACC_PLAIN>(P, torque, (double*)grid, st, tiled);
+    if (P->kahan == 1) return spread_r<float, ACC_KAHAN>(P, torque, (float*)grid, st, tiled);
+    if (P->kahan == 2) return spread_r<float, ACC_WIDE>(P, torque, (float*)grid, st, tiled);
+    return spread_r<float, ACC_PLAIN>(P, torque, (float*)grid, st, tiled);
 }
 
 hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, double* W,

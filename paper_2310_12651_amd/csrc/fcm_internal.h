@@ -179,14 +179,16 @@ hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const d
 hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const double* F,
                               const double* T, hipStream_t st);
 
-hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st);
+// tiled: write the field in the x-y tiled layout of launch_solve
+hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st,
+                         bool tiled = false);
 // tiled: the field is in the x-y tiled layout written by launch_solve(..., tiled)
 hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, double* W,
                          hipStream_t st, bool tiled = false);
 // ev: NULL or 6 events recorded before/between/after the five FFT passes
-// tiled: write the velocity field in the x-y tiled layout (tiles of 8 x by 4 y,
-// x fastest inside a tile, tiles x fastest, then tile rows, then z) when the
-// plan supports it (solve_tiles); the result says whether it did
+// tiled: the force field arrives, and the velocity field leaves, in the x-y
+// tiled layout (tiles of 8 x by 4 y, x fastest inside a tile, tiles x fastest,
+// then tile rows, then z); only when the plan supports it (solve_tiles)
 hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st,
                         hipEvent_t* ev = nullptr, bool tiled = false);
 bool solve_tiles(const fcm_plan_impl* P);
