@@ -133,13 +133,15 @@ int fcm_plan_footprint(int64_t N, int grid, int precision, int64_t* bytes);
  * non-finite position, else FCM_OK; clears the flag. */
 int fcm_plan_last_error(fcm_plan_t p);
 /*
- * Per-stage timing with HIP events recorded on the call's stream.  When enabled,
- * every fcm_mobility call records FCM_NUM_STAGES + 1 events (up to 4096 calls are
- * kept); fcm_plan_stage_times synchronises, adds the elapsed milliseconds of each
- * stage over the recorded calls into ms_out[0..FCM_NUM_STAGES), stores the number
- * of calls in *ncalls, and clears the record.  Stages, in order: sort (hash, scan,
- * scatter, record gather), spread, FFT x forward, FFT y forward, FFT z + projection,
- * FFT y inverse, FFT x inverse, interpolation, pair correction (gather + pairs).
+ * Per-stage timing with HIP events.  When enabled, every fcm_mobility call records
+ * its stage boundaries (up to 1024 calls are kept); fcm_plan_stage_times
+ * synchronises, adds the elapsed milliseconds of each stage over the recorded
+ * calls into ms_out[0..FCM_NUM_STAGES), stores the number of calls in *ncalls, and
+ * clears the record.  Stages, in order: sort (hash, scan, scatter, records),
+ * spread, FFT x forward, FFT y forward, FFT z + projection, FFT y inverse, FFT x
+ * inverse, interpolation, pair correction.  The pair correction runs on a second
+ * stream of the plan, beside spread and FFT, so the first eight stages add up to
+ * the call and the ninth overlaps them.
  */
 #define FCM_NUM_STAGES 9
 int fcm_plan_set_timing(fcm_plan_t p, int enable);

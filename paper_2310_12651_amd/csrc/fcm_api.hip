@@ -129,7 +129,9 @@ size_t grid_rec_size(int precision) {
 }
 
 constexpr int kMaxTimedCalls = 1024;
-constexpr int kEvPerCall = FCM_NUM_STAGES + 1;
+// events per call: stage boundaries 0..8 and the end of the call (9) on the call's
+// stream, then the start and end of the pair correction (10, 11) on the side stream
+constexpr int kEvPerCall = FCM_NUM_STAGES + 3;
 
 void free_events(fcm_plan_impl* P) {
     if (!P->events) return;
@@ -152,9 +154,12 @@ void free_plan(fcm_plan_impl* P) {
     free_events(P);
     void* bufs[] = {P->grid,  P->twid, P->counts, P->starts,    P->keys,       P->ranks,
                     P->perm,  P->scan_tmp, P->grec, P->prec,    P->ppos,       P->flag,
-                    P->pair_hits, P->pair_count};
+                    P->pair_hits, P->pair_count, P->corr};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    if (P->fork) (void)hipEventDestroy(P->fork);
+    if (P->join) (void)hipEventDestroy(P->join);
+    if (P->side) (void)hipStreamDestroy(P->side);
     delete P;
 }
 
@@ -299,8 +304,12 @@ int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
     FCM_ALLOC(P->ppos, (size_t)ncap * sizeof(double4));
     FCM_ALLOC(P->pair_hits, (size_t)3 * ncap * kPairCap * sizeof(int));
     FCM_ALLOC(P->pair_count, (size_t)3 * ncap * sizeof(int));
+    FCM_ALLOC(P->corr, (size_t)6 * ncap * sizeof(double));
     FCM_ALLOC(P->flag, 16 * sizeof(int));
 #undef FCM_ALLOC
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->join, hipEventDisableTiming);
     if (e != hipSuccess) return map_err(e);
     // twiddles exp(-2 pi i m / M) in extended precision, rounded once
     const size_t n = (size_t)grid * 2;
@@ -354,6 +363,7 @@ int64_t plan_bytes(int64_t ncap, int grid, int precision, int cellcap, int nbins
     int64_t b = 3 * M * M * M * rs + M * 2 * rs;
     b += 6 * ncap * (int64_t)sizeof(int);
     b += 3 * ncap * (int64_t)(kPairCap + 1) * (int64_t)sizeof(int);
+    b += 6 * ncap * (int64_t)sizeof(double);
     b += ncap * (int64_t)(grid_rec_size(precision) + sizeof(PairRec) + sizeof(double4));
     b += (int64_t)(2 * (nbins + 1) + 2 * (cellcap + 1)) * (int64_t)sizeof(int) + 2048 * 4 + 64;
     return b;
@@ -446,14 +456,30 @@ int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double*
     if (e == hipSuccess)
         e = corr ? launch_gather_both(p, pos, F, T, st) : launch_gather_grid(p, pos, F, T, st);
     mark(1);
+    // The pair correction depends only on the sorted records: it runs on the
+    // plan's side stream while spread and FFT run here, into the plan's
+    // correction buffer, which the interpolation adds to its results.
+    if (e == hipSuccess && corr) {
+        e = hipEventRecord(p->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
+        if (ev && e == hipSuccess) (void)hipEventRecord(ev[10], p->side);
+        if (e == hipSuccess)
+            e = launch_pair(p, p->corr, Omega ? p->corr + 3 * p->N : nullptr, T != nullptr, p->side,
+                            true);
+        if (ev && e == hipSuccess) (void)hipEventRecord(ev[11], p->side);
+        if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
+    } else if (ev) {
+        (void)hipEventRecord(ev[10], st);
+        (void)hipEventRecord(ev[11], st);
+    }
     // the field stays inside the call, so spread, solve and interpolation may
     // pass it along in the tiled layout
     const bool tiled = solve_tiles(p);
     if (e == hipSuccess) e = launch_spread(p, T != nullptr, p->grid, st, tiled);
     if (e == hipSuccess) e = launch_solve(p, p->grid, st, ev ? ev + 2 : nullptr, tiled);
-    if (e == hipSuccess) e = launch_interp(p, p->grid, V, Omega, st, tiled);
+    if (e == hipSuccess && corr) e = hipStreamWaitEvent(st, p->join, 0);
+    if (e == hipSuccess) e = launch_interp(p, p->grid, V, Omega, st, tiled, corr ? p->corr : nullptr);
     mark(8);
-    if (e == hipSuccess && corr) e = launch_pair(p, V, Omega, T != nullptr, st);
     mark(9);
     return map_err(e);
 }
@@ -485,14 +511,16 @@ int fcm_plan_stage_times(fcm_plan_t p, double* ms_out, int* ncalls) {
     for (int s = 0; s < FCM_NUM_STAGES; ++s) ms_out[s] = 0.0;
     const int n = p->events ? p->ev_calls : 0;
     if (n > 0) {
-        hipError_t e = hipEventSynchronize(p->events[(size_t)(n - 1) * kEvPerCall + kEvPerCall - 1]);
+        hipError_t e = hipEventSynchronize(p->events[(size_t)(n - 1) * kEvPerCall + 9]);
         if (e != hipSuccess) return map_err(e);
     }
     for (int c = 0; c < n; ++c) {
         hipEvent_t* ev = p->events + (size_t)c * kEvPerCall;
         for (int s = 0; s < FCM_NUM_STAGES; ++s) {
+            // the pair correction (last stage) is timed on the side stream
+            const int b = s == FCM_NUM_STAGES - 1 ? 10 : s, t = s == FCM_NUM_STAGES - 1 ? 11 : s + 1;
             float ms = 0.0f;
-            hipError_t e = hipEventElapsedTime(&ms, ev[s], ev[s + 1]);
+            hipError_t e = hipEventElapsedTime(&ms, ev[b], ev[t]);
             if (e != hipSuccess) return map_err(e);
             ms_out[s] += ms;
         }

@@ -343,7 +343,8 @@ template <typename R, bool OMEGA, bool SAMEW>
 __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ rec,
                                                 const R* __restrict__ grid, double* __restrict__ V,
                                                 double* __restrict__ W, GridArgs<R> a,
-                                                double scaleV, double scaleW) {
+                                                double scaleV, double scaleW,
+                                                const double* __restrict__ corr) {
     __shared__ ZTab<R> zt[4][kMaxSupport];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -447,13 +448,21 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
     }
     if (live && lane == 0) {
         const int64_t n = r.orig;
-        V[3 * n + 0] = (double)v0 * scaleV;
-        V[3 * n + 1] = (double)v1 * scaleV;
-        V[3 * n + 2] = (double)v2 * scaleV;
+        double cv[3] = {0, 0, 0}, cw[3] = {0, 0, 0};
+        if (corr) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                cv[d] = corr[3 * n + d];
+                cw[d] = corr[3 * (int64_t)a.N + 3 * n + d];
+            }
+        }
+        V[3 * n + 0] = (double)v0 * scaleV + cv[0];
+        V[3 * n + 1] = (double)v1 * scaleV + cv[1];
+        V[3 * n + 2] = (double)v2 * scaleV + cv[2];
         if (OMEGA) {
-            W[3 * n + 0] = (double)o0 * scaleW;
-            W[3 * n + 1] = (double)o1 * scaleW;
-            W[3 * n + 2] = (double)o2 * scaleW;
+            W[3 * n + 0] = (double)o0 * scaleW + cw[0];
+            W[3 * n + 1] = (double)o1 * scaleW + cw[1];
+            W[3 * n + 2] = (double)o2 * scaleW + cw[2];
         }
     }
 }
@@ -478,7 +487,8 @@ template <bool OMEGA>
 __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restrict__ rec,
                                                  const float* __restrict__ grid, double* __restrict__ V,
                                                  double* __restrict__ W, GridArgs<float> a,
-                                                 double scaleV, double scaleW) {
+                                                 double scaleV, double scaleW,
+                                                 const double* __restrict__ corr) {
     __shared__ ZTab<float> zt[4][kMaxSupport];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -580,13 +590,21 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
     }
     if (live && lane == 0) {
         const int64_t n = r.orig;
-        V[3 * n + 0] = (double)v0 * scaleV;
-        V[3 * n + 1] = (double)v1 * scaleV;
-        V[3 * n + 2] = (double)v2 * scaleV;
+        double cv[3] = {0, 0, 0}, cw[3] = {0, 0, 0};
+        if (corr) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                cv[d] = corr[3 * n + d];
+                cw[d] = corr[3 * (int64_t)a.N + 3 * n + d];
+            }
+        }
+        V[3 * n + 0] = (double)v0 * scaleV + cv[0];
+        V[3 * n + 1] = (double)v1 * scaleV + cv[1];
+        V[3 * n + 2] = (double)v2 * scaleV + cv[2];
         if (OMEGA) {
-            W[3 * n + 0] = (double)o0 * scaleW;
-            W[3 * n + 1] = (double)o1 * scaleW;
-            W[3 * n + 2] = (double)o2 * scaleW;
+            W[3 * n + 0] = (double)o0 * scaleW + cw[0];
+            W[3 * n + 1] = (double)o1 * scaleW + cw[1];
+            W[3 * n + 2] = (double)o2 * scaleW + cw[2];
         }
     }
 }
@@ -657,7 +675,7 @@ hipError_t spread_r(const fcm_plan_impl* P, bool torque, R* grid, hipStream_t st
 
 template <typename R>
 hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W, hipStream_t st,
-                    bool tiled) {
+                    bool tiled, const double* corr) {
     GridArgs<R> a = make_args<R>(P);
     a.tiled = tiled ? 1 : 0;
     const double pi = 3.14159265358979323846;
@@ -670,18 +688,18 @@ hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W,
     if constexpr (sizeof(R) == sizeof(float)) {
         if (P->M % 4 == 0 && P->MG <= 13 && a.same_width) {
             if (W == nullptr)
-                hipLaunchKernelGGL(k_interp4<false>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+                hipLaunchKernelGGL(k_interp4<false>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
             else
-                hipLaunchKernelGGL(k_interp4<true>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+                hipLaunchKernelGGL(k_interp4<true>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
             return hipGetLastError();
         }
     }
     if (W == nullptr)
-        hipLaunchKernelGGL((k_interp<R, false, true>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+        hipLaunchKernelGGL((k_interp<R, false, true>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
     else if (a.same_width)
-        hipLaunchKernelGGL((k_interp<R, true, true>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+        hipLaunchKernelGGL((k_interp<R, true, true>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
     else
-        hipLaunchKernelGGL((k_interp<R, true, false>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW);
+        hipLaunchKernelGGL((k_interp<R, true, false>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
     return hipGetLastError();
 }
 
@@ -697,9 +715,10 @@ hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStr
 }
 
 hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, double* W,
-                         hipStream_t st, bool tiled) {
-    if (P->precision == FCM_FP64) return interp_r<double>(P, (const double*)grid, V, W, st, tiled);
-    return interp_r<float>(P, (const float*)grid, V, W, st, tiled);
+                         hipStream_t st, bool tiled, const double* corr) {
+    if (P->precision == FCM_FP64)
+        return interp_r<double>(P, (const double*)grid, V, W, st, tiled, corr);
+    return interp_r<float>(P, (const float*)grid, V, W, st, tiled, corr);
 }
 
 }  // namespace fcm

@@ -108,6 +108,7 @@ struct PairArgs {
     double eta, sigma, sigmaD, Sigma, SigmaD;
     double selfVF, selfOT;
     int with_pairs;                // 0 = only self corrections (R_c = 0)
+    int store;                     // 1 = write the corrections, 0 = add them
     // the six Gaussian widths of the corrections: squared width s, erfc
     // argument scale 1/sqrt(2 s), exponent scale -1/(2 s), norm (2 pi s)^(-3/2)
     double wsq[6], escale[6], gexp[6], gnorm[6];
@@ -149,6 +150,9 @@ struct fcm_plan_impl {
     double4* ppos;         // N wrapped positions in pair order (w unused)
     int* pair_hits;        // 3N x kPairCap neighbours found by the pair scan
     int* pair_count;       // 3N neighbour counts
+    double* corr;          // 6N: pair + self corrections of V (3N) then Omega (3N)
+    hipStream_t side;      // the pair correction runs here, beside spread and FFT
+    hipEvent_t fork, join; // sorted records ready / corrections ready
     int* flag;             // [0] = non-finite position seen
     hipStream_t last_stream;
     int counts_dirty;      // counts may be non-zero (cleared by the next sort)
@@ -182,9 +186,10 @@ hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const d
 // tiled: write the field in the x-y tiled layout of launch_solve
 hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st,
                          bool tiled = false);
-// tiled: the field is in the x-y tiled layout written by launch_solve(..., tiled)
+// tiled: the field is in the x-y tiled layout written by launch_solve(..., tiled);
+// corr: NULL, or corrections added to the results (V part, then Omega part at + 3N)
 hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, double* W,
-                         hipStream_t st, bool tiled = false);
+                         hipStream_t st, bool tiled = false, const double* corr = nullptr);
 // ev: NULL or 6 events recorded before/between/after the five FFT passes
 // tiled: the force field arrives, and the velocity field leaves, in the x-y
 // tiled layout (tiles of 8 x by 4 y, x fastest inside a tile, tiles x fastest,
@@ -192,8 +197,9 @@ hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, do
 hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st,
                         hipEvent_t* ev = nullptr, bool tiled = false);
 bool solve_tiles(const fcm_plan_impl* P);
+// store: write the corrections to V and W (else add them)
 hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool torque,
-                       hipStream_t st);
+                       hipStream_t st, bool store = false);
 
 // plan construction pieces (fcm_api.hip), shared with the request server
 int fft_maxe(int precision, bool zpass);

@@ -328,13 +328,23 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restr
             w[2] += res[tid + l][5];
         }
         const int64_t n = me.orig;
-        V[3 * n + 0] += a.selfVF * me.F[0] + v[0];
-        V[3 * n + 1] += a.selfVF * me.F[1] + v[1];
-        V[3 * n + 2] += a.selfVF * me.F[2] + v[2];
-        if (W) {
-            W[3 * n + 0] += a.selfOT * me.T[0] + w[0];
-            W[3 * n + 1] += a.selfOT * me.T[1] + w[1];
-            W[3 * n + 2] += a.selfOT * me.T[2] + w[2];
+        const double c[6] = {a.selfVF * me.F[0] + v[0], a.selfVF * me.F[1] + v[1],
+                             a.selfVF * me.F[2] + v[2], a.selfOT * me.T[0] + w[0],
+                             a.selfOT * me.T[1] + w[1], a.selfOT * me.T[2] + w[2]};
+        if (a.store) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) V[3 * n + d] = c[d];
+            if (W) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) W[3 * n + d] = c[3 + d];
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) V[3 * n + d] += c[d];
+            if (W) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) W[3 * n + d] += c[3 + d];
+            }
         }
     }
 }
@@ -342,7 +352,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restr
 }  // namespace
 
 hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torque*/,
-                       hipStream_t st) {
+                       hipStream_t st, bool store) {
     PairArgs a;
     a.N = (int)P->N;
     a.m = P->m;
@@ -357,6 +367,7 @@ hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torq
     a.selfVF = P->selfVF;
     a.selfOT = P->selfOT;
     a.with_pairs = P->rc > 0.0 ? 1 : 0;
+    a.store = store ? 1 : 0;
     const int* cs = P->starts + P->nbins + 1;
     if (a.with_pairs)
         hipLaunchKernelGGL(k_pair_scan, dim3((3 * a.N + kScanBlock - 1) / kScanBlock), dim3(kScanBlock),
