@@ -65,7 +65,7 @@ def algorithmic_bytes(w, stage):
 
 KERNEL_OF_STAGE = {"spread": "k_spread", "fft_x_fwd": "k_fft_x_r2c_reg", "fft_y_fwd": "k_fft_y_reg",
                    "fft_z_solve": "k_fft_z_solve_reg", "fft_y_inv": "k_fft_y_reg",
-                   "fft_x_inv": "k_fft_x_c2r_reg", "interp": "k_interp", "pair": "k_pair_eval",
+                   "fft_x_inv": "k_fft_x_c2r_reg", "interp": "k_interp4", "pair": "k_pair_eval",
                    "sort": "k_hash"}
 SOURCE_OF_STAGE = {"spread": "fcm_grid.hip", "interp": "fcm_grid.hip", "pair": "fcm_pair.hip",
                    "sort": "fcm_sort.hip"}
