@@ -77,10 +77,15 @@ int fcm_options_default(fcm_options* opt);
 /*
  * Create a plan for N particles of radius a in the periodic cube [0, L)^3.
  *   sigma_delta : Sigma, width of the modified Gaussian (Sec. 3); Sigma >= sigma
- *                 = a / sqrt(pi).  Sigma == sigma is standard FCM (no correction).
+ *                 = a / sqrt(pi).  Sigma == sigma is standard FCM (no correction);
+ *                 widths within 1e-12 (relative) of sigma, and torque widths
+ *                 (fcm_options.sigma_D_grid) within 1e-12 of sigma_D, count as
+ *                 equal to them.
  *   grid        : grid points per axis, an even 2^p 3^q between 8 and 1024
  *                 (dx = L / grid).
- *   r_cut       : R_c, pair-correction cut-off (Sec. 4); 0 <= R_c < L/2.
+ *   r_cut       : R_c, pair-correction cut-off (Sec. 4); 0 <= R_c < L/2.  R_c = 0:
+ *                 no pair search (only the self corrections of App. B, which
+ *                 vanish for standard FCM).
  * Allocates every device buffer the plan needs on the current HIP device;
  * later calls allocate nothing.
  * Errors: FCM_EINVAL if N <= 0, L <= 0, a <= 0, Sigma < sigma, the grid is not
@@ -124,7 +129,8 @@ int fcm_interp(fcm_plan_t p, const double* pos, const void* grid_in,
 int fcm_correct(fcm_plan_t p, const double* pos, const double* F, const double* T,
                 double* V, double* Omega, void* stream);
 
-/* Plan properties. */
+/* Plan properties.  cells_per_axis: m = max(int(L/R_c), 3) pair cells per axis
+ * (Sec. 4), at most 128; 1 when R_c = 0 (no pair search). */
 int fcm_plan_info(fcm_plan_t p, int64_t* N, int* grid, int* support, int* precision,
                   int* cells_per_axis);
 /* Device bytes a plan with these sizes would allocate (for admission control). */

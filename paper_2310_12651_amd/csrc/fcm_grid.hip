@@ -609,6 +609,168 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
     }
 }
 
+// FP32 interpolation with several particles per wavefront (M divisible by 4,
+// M_G <= 13, Sigma_D = Sigma, one field component addressable with 32-bit byte
+// offsets).  Lane 32 h + M_G g + j serves particle slot g (g < 32 / M_G, at
+// most four slots), support row j and two aligned quads of four x points (two
+// 16-byte loads; lane h = 0 and h = 1 of a row together cover x0 & ~3 plus 0..15),
+// so at M_G = 10 three particles share a wavefront and 60 of its 64 lanes work.  The per-lane sums follow the factorisation of
+// k_interp4; the two chunks of a row are combined by one lane exchange, the
+// rows of each particle through LDS, in a fixed order.
+template <bool OMEGA>
+__global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restrict__ rec,
+                                                 const float* __restrict__ grid, double* __restrict__ V,
+                                                 double* __restrict__ W, GridArgs<float> a,
+                                                 double scaleV, double scaleW,
+                                                 const double* __restrict__ corr) {
+    constexpr int kSlots = 4;
+    constexpr int NV = OMEGA ? 6 : 3;
+    __shared__ ZTab<float> zt[4][kSlots][kMaxSupport];
+    __shared__ float red[4][NV][32];
+    __shared__ int origs[4][kSlots];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int M = a.M, MG = a.MG;
+    const int ppw = min(kSlots, 32 / MG);
+    const int h = lane >> 5, r = lane & 31;
+    const int g = r / MG, j = r - g * MG;
+    const bool slot = g < ppw;
+    const int64_t pb = ((int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + wave) * ppw;
+    const int64_t p = pb + g;
+    const bool live = slot && p < a.N;
+    const GridRec<float> rv = rec[live ? p : a.N - 1];
+    const int gz = slot ? g : 0;
+    const float dx = a.dx;
+    if (slot && h == 0) {
+        ZTab<float> e = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (live) {
+            const float d = ((float)j - rv.f[2]) * dx;
+            const float d2 = d * d;
+            e.g = fexp2(-d2 * a.e2);
+            e.gd2 = e.g * d2;
+            e.gD = e.g;
+            e.gDd = e.g * d;
+        }
+        zt[wave][g][j] = e;
+        if (j == 0) origs[wave][g] = rv.orig;
+    }
+    // Row j of the support; the lane's two quads of four x points, counted in
+    // quads from x0 & ~3.  The pairing makes each of the two loads of a
+    // wavefront cover whole 8 x 4 tiles where it can: with the first quad at
+    // an even position both lanes of a row read the same tile in each load.
+    const int x0 = rv.s[0], off0 = x0 & 3;
+    const bool odd = (x0 >> 2) & 1;
+    const int oa = odd ? 1 + h : h, ob = odd ? 3 - 3 * h : 2 + h;
+    int xa = (x0 - off0) + 4 * oa;
+    if (xa >= M) xa -= M;
+    int xb = (x0 - off0) + 4 * ob;
+    if (xb >= M) xb -= M;
+    int yy = rv.s[1] + j;
+    if (yy >= M) yy -= M;
+    const float dyv = ((float)j - rv.f[1]) * dx;
+    const float gy = fexp2(-dyv * dyv * a.e2);
+    float gw[8], gwd[8], gwd2[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int i = 4 * (e < 4 ? oa : ob) + (e & 3) - off0;
+        const float dxe = ((float)i - rv.f[0]) * dx;
+        const float gx = (i >= 0 && i < MG) ? fexp2(-dxe * dxe * a.e2) : 0.0f;
+        gw[e] = gx * gy;
+        gwd[e] = gw[e] * dxe;
+        gwd2[e] = gwd[e] * dxe;
+    }
+    auto colof = [&](int x) {
+        return (a.tiled ? (unsigned)((yy >> 2) * (M << 2) + ((x >> 3) << 5) + ((yy & 3) << 3) + (x & 7))
+                        : (unsigned)yy * (unsigned)M + (unsigned)x) *
+               4u;
+    };
+    const unsigned cola = colof(xa), colb = colof(xb);
+    // quads of four x points that meet the support [0, M_G)
+    const bool needa = live && 4 * oa - off0 < MG;
+    const bool needb = live && 4 * ob - off0 < MG;
+    const size_t M3 = (size_t)M * M * M;
+    const int bytes = (int)(M3 * sizeof(float));
+    const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(grid), (short)0, bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(grid + M3), (short)0, bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rs2 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(grid + 2 * M3), (short)0, bytes, kBufferWord3);
+    const unsigned plane = (unsigned)M * (unsigned)M * 4u;
+    int z = rv.s[2];
+    unsigned zoff = (unsigned)z * plane;
+    __syncthreads();
+    float P[3] = {0, 0, 0}, Rr[3] = {0, 0, 0}, PD2[3] = {0, 0, 0}, PD[2] = {0, 0}, Q[2] = {0, 0};
+    for (int k = 0; k < MG; ++k) {
+        const ZTab<float> e = zt[wave][gz][k];
+        float4 u[3][2];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) u[cc][0] = u[cc][1] = make_float4(0, 0, 0, 0);
+        if (needa) {
+            u[0][0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs0, (int)(zoff + cola), 0, 0));
+            u[1][0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs1, (int)(zoff + cola), 0, 0));
+            u[2][0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs2, (int)(zoff + cola), 0, 0));
+        }
+        if (needb) {
+            u[0][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs0, (int)(zoff + colb), 0, 0));
+            u[1][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs1, (int)(zoff + colb), 0, 0));
+            u[2][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs2, (int)(zoff + colb), 0, 0));
+        }
+        if (++z == M) {
+            z = 0;
+            zoff = 0;
+        } else {
+            zoff += plane;
+        }
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const float4 ua = u[cc][0], ub = u[cc][1];
+            const float pc = gw[0] * ua.x + gw[1] * ua.y + gw[2] * ua.z + gw[3] * ua.w +
+                             gw[4] * ub.x + gw[5] * ub.y + gw[6] * ub.z + gw[7] * ub.w;
+            const float rc = gwd2[0] * ua.x + gwd2[1] * ua.y + gwd2[2] * ua.z + gwd2[3] * ua.w +
+                             gwd2[4] * ub.x + gwd2[5] * ub.y + gwd2[6] * ub.z + gwd2[7] * ub.w;
+            P[cc] += e.g * pc;
+            Rr[cc] += e.g * rc;
+            PD2[cc] += e.gd2 * pc;
+            if (OMEGA) {
+                if (cc < 2) PD[cc] += e.gDd * pc;
+                if (cc > 0) {
+                    const float qc = gwd[0] * ua.x + gwd[1] * ua.y + gwd[2] * ua.z + gwd[3] * ua.w +
+                                     gwd[4] * ub.x + gwd[5] * ub.y + gwd[6] * ub.z + gwd[7] * ub.w;
+                    Q[cc - 1] += e.g * qc;
+                }
+            }
+        }
+    }
+    const float cy = a.A + a.B * dyv * dyv;
+    float vals[NV];
+    vals[0] = cy * P[0] + a.B * (Rr[0] + PD2[0]);
+    vals[1] = cy * P[1] + a.B * (Rr[1] + PD2[1]);
+    vals[2] = cy * P[2] + a.B * (Rr[2] + PD2[2]);
+    if constexpr (OMEGA) {
+        vals[3] = dyv * P[2] - PD[1];
+        vals[4] = PD[0] - Q[1];
+        vals[5] = Q[0] - dyv * P[0];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) vals[v] += __shfl_xor(vals[v], 32, 64);
+    if (h == 0 && slot) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) red[wave][v][r] = vals[v];
+    }
+    __syncthreads();
+    if (lane < ppw * NV) {
+        const int gg = lane / NV, v = lane - gg * NV;
+        if (pb + gg < a.N) {
+            float sum = 0.0f;
+            for (int jj = 0; jj < MG; ++jj) sum += red[wave][v][gg * MG + jj];
+            const int64_t n = origs[wave][gg];
+            if (v < 3) {
+                V[3 * n + v] = (double)sum * scaleV + (corr ? corr[3 * n + v] : 0.0);
+            } else {
+                W[3 * n + v - 3] = (double)sum * scaleW + (corr ? corr[3 * (int64_t)a.N + 3 * n + v - 3] : 0.0);
+            }
+        }
+    }
+}
+
 template <typename R>
 GridArgs<R> make_args(const fcm_plan_impl* P) {
     GridArgs<R> a;
@@ -686,6 +848,15 @@ hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W,
     dim3 g((unsigned)((P->N + 3) / 4)), b(256);
     const GridRec<R>* rec = (const GridRec<R>*)P->grec;
     if constexpr (sizeof(R) == sizeof(float)) {
+        if (P->M % 4 == 0 && P->MG <= 13 && a.same_width && P->M <= 512) {
+            const int ppw = std::min(4, 32 / P->MG);
+            dim3 g8((unsigned)((P->N + 4 * ppw - 1) / (4 * ppw)));
+            if (W == nullptr)
+                hipLaunchKernelGGL(k_interp8<false>, g8, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
+            else
+                hipLaunchKernelGGL(k_interp8<true>, g8, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
+            return hipGetLastError();
+        }
         if (P->M % 4 == 0 && P->MG <= 13 && a.same_width) {
             if (W == nullptr)
                 hipLaunchKernelGGL(k_interp4<false>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);

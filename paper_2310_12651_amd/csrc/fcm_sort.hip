@@ -5,7 +5,9 @@
 //
 // The counting sort places particles with atomics and then orders every
 // segment by original index, so the sorted order is (key, original index):
-// deterministic from run to run.  The records are built in the caller's
+// deterministic from run to run.  Short segments are ordered by one thread
+// each; longer ones (dense bins, large pair cells) by a workgroup each.  With
+// no pair search (R_c = 0) the pair order is the caller's order.  The records are built in the caller's
 // order (coalesced reads of positions, forces and torques) and stored at each
 // particle's sorted position through the inverse permutation.
 #include "fcm_internal.h"
@@ -23,8 +25,13 @@ struct HashArgs {
     int N, M, MG;
     int TX, TY, TZ, nbx, nby, nbz, nbins;
     int m;
+    int ident;                     // pair order = caller's order (no cell search)
     double L, dx, cw;
 };
+
+constexpr int kShortSegment = 64;      // ordered by one thread
+constexpr int kLdsSegment = 8192;      // ordered by a bitonic sort in LDS
+constexpr int kLongBlocks = 128;       // workgroups of the long-segment pass
 
 // wrap into [0, L); non-finite values, and values too large for the wrap to
 // land in [0, L), become 0 and raise the plan's flag.  Every index derived
@@ -79,7 +86,12 @@ __global__ void k_hash(const double* __restrict__ pos, HashArgs h, int* __restri
     keys[i] = bin;
     keys[h.N + i] = cell;
     ranks[i] = atomicAdd(&counts[bin], 1);
-    ranks[h.N + i] = atomicAdd(&counts[h.nbins + cell], 1);
+    if (h.ident) {
+        ranks[h.N + i] = i;
+        if (i == 0) counts[h.nbins] = h.N;
+    } else {
+        ranks[h.N + i] = atomicAdd(&counts[h.nbins + cell], 1);
+    }
 }
 
 // block-wide inclusive scan of one int per thread (blockDim = NT)
@@ -184,30 +196,46 @@ __global__ __launch_bounds__(kScanThreads) void k_scan2_down(int* __restrict__ c
 
 __global__ void k_scatter(const int* __restrict__ keys, const int* __restrict__ ranks,
                           const int* __restrict__ start_bin, const int* __restrict__ start_cell,
-                          int* __restrict__ perm, int N) {
+                          int* __restrict__ perm, int N, int* __restrict__ nlong) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *nlong = 0;
     if (i >= N) return;
     perm[start_bin[keys[i]] + ranks[i]] = i;
     perm[N + start_cell[keys[N + i]] + ranks[N + i]] = i;
 }
 
-// order each segment of perm by value (insertion sort): segments 0..nbins-1
-// are the grid bins (perm[0..N)), the next ncells the pair cells (perm[N..2N));
-// then record the inverse permutation: inv[perm[j]] = j (inv[N + ...] for cells)
-__global__ void k_segment_order(const int* __restrict__ starts, int nbins, int ncells, int N,
-                                int* __restrict__ perm, int* __restrict__ inv) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nbins + ncells) return;
+// Segment s of the sort: grid bins 0..nbins-1 (perm[0..N)), then pair cells
+// (perm[N..2N)).  Returns the bounds [b, e) and the arrays of its half.
+__device__ inline void segment(int s, const int* starts, int nbins, int N, int* perm, int* inv,
+                               int* b, int* e, int** pm, int** iv) {
     const int* start = starts;
-    int* pm = perm;
-    int* iv = inv;
+    *pm = perm;
+    *iv = inv;
     if (s >= nbins) {
         s -= nbins;
         start = starts + nbins + 1;
-        pm = perm + N;
-        iv = inv + N;
+        *pm = perm + N;
+        *iv = inv + N;
     }
-    const int b = start[s], e = start[s + 1];
+    *b = start[s];
+    *e = start[s + 1];
+}
+
+// Order each segment of perm by value and record the inverse permutation
+// inv[perm[j]] = j.  A thread orders a short segment by insertion; longer
+// segments are listed for k_segment_order_long.
+__global__ void k_segment_order(const int* __restrict__ starts, int nbins, int nseg, int N,
+                                int* __restrict__ perm, int* __restrict__ inv,
+                                int* __restrict__ longlist, int* __restrict__ nlong) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    int b, e;
+    int *pm, *iv;
+    segment(s, starts, nbins, N, perm, inv, &b, &e, &pm, &iv);
+    if (e - b > kShortSegment) {
+        longlist[atomicAdd(nlong, 1)] = s;
+        return;
+    }
     for (int i = b + 1; i < e; ++i) {
         const int v = pm[i];
         int j = i - 1;
@@ -218,6 +246,77 @@ __global__ void k_segment_order(const int* __restrict__ starts, int nbins, int n
         pm[j + 1] = v;
     }
     for (int i = b; i < e; ++i) iv[pm[i]] = i;
+}
+
+// The listed long segments, one workgroup each (blocks stride over the list,
+// whose length is fixed by the previous launch).  Up to kLdsSegment members:
+// bitonic sort in LDS.  Beyond: every member's rank is the number of smaller
+// members, counted against copies of the segment staged through LDS (tmp
+// holds the copy, indexed like perm).
+__global__ __launch_bounds__(256) void k_segment_order_long(const int* __restrict__ starts,
+                                                            int nbins, int N, int* __restrict__ perm,
+                                                            int* __restrict__ inv,
+                                                            const int* __restrict__ longlist,
+                                                            const int* __restrict__ nlong,
+                                                            int* __restrict__ tmp) {
+    __shared__ int sh[kLdsSegment];
+    const int count = *nlong;
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+        int b, e;
+        int *pm, *iv;
+        const int s = longlist[q];
+        segment(s, starts, nbins, N, perm, inv, &b, &e, &pm, &iv);
+        const int n = e - b;
+        if (n <= kLdsSegment) {
+            int p2 = 1;
+            while (p2 < n) p2 <<= 1;
+            for (int i = t; i < p2; i += nt) sh[i] = i < n ? pm[b + i] : 0x7fffffff;
+            __syncthreads();
+            for (int k = 2; k <= p2; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int i = t; i < p2; i += nt) {
+                        const int l = i ^ j;
+                        if (l > i) {
+                            const int x = sh[i], y = sh[l];
+                            const bool up = (i & k) == 0;
+                            if ((x > y) == up) {
+                                sh[i] = y;
+                                sh[l] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int i = t; i < n; i += nt) {
+                const int v = sh[i];
+                pm[b + i] = v;
+                iv[v] = b + i;
+            }
+        } else {
+            int* tp = tmp + (pm - perm);
+            for (int i = t; i < n; i += nt) tp[b + i] = pm[b + i];
+            __syncthreads();
+            for (int r0 = 0; r0 < n; r0 += nt) {
+                const int i = r0 + t;
+                const int v = i < n ? tp[b + i] : 0x7fffffff;
+                int rank = 0;
+                for (int c0 = 0; c0 < n; c0 += kLdsSegment) {
+                    const int cn = min(kLdsSegment, n - c0);
+                    __syncthreads();
+                    for (int k = t; k < cn; k += nt) sh[k] = tp[b + c0 + k];
+                    __syncthreads();
+                    for (int k = 0; k < cn; ++k) rank += sh[k] < v;
+                }
+                if (i < n) {
+                    pm[b + rank] = v;
+                    iv[v] = b + rank;
+                }
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // Per-particle records in sorted order, built in the caller's order: thread i
@@ -292,6 +391,7 @@ hipError_t launch_hash(const fcm_plan_impl* P, const double* pos, hipStream_t st
     h.nbz = P->nbz;
     h.nbins = P->nbins;
     h.m = P->m;
+    h.ident = P->rc > 0.0 ? 0 : 1;
     h.L = P->L;
     h.dx = P->dx;
     h.cw = P->L / P->m;
@@ -315,11 +415,18 @@ hipError_t launch_scatter(const fcm_plan_impl* P, hipStream_t st) {
     int N = (int)P->N;
     const int* sb = P->starts;
     const int* sc = P->starts + P->nbins + 1;
+    int* nlong = P->flag + 1;
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(N, 256)), dim3(256), 0, st, P->keys, P->ranks, sb,
-                       sc, P->perm, N);
-    // the ranks are dead after the scatter: their buffer takes the inverse permutation
-    hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(P->nbins + P->ncells, 256)), dim3(256), 0,
-                       st, P->starts, P->nbins, P->ncells, N, P->perm, P->ranks);
+                       sc, P->perm, N, nlong);
+    // The ranks are dead after the scatter: their buffer takes the inverse
+    // permutation.  Without a pair search the pair order is the identity, which
+    // the hash already wrote there.
+    const int nseg = P->nbins + (P->rc > 0.0 ? P->ncells : 0);
+    hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, P->starts,
+                       P->nbins, nseg, N, P->perm, P->ranks, P->seglong, nlong);
+    // pair_hits is free until the pair pass (which runs after the records are built)
+    hipLaunchKernelGGL(k_segment_order_long, dim3(kLongBlocks), dim3(256), 0, st, P->starts, P->nbins,
+                       N, P->perm, P->ranks, P->seglong, nlong, P->pair_hits);
     return hipGetLastError();
 }
 

@@ -190,3 +190,75 @@ def test_nonfinite_position_is_reported():
     plan.mobility(dev(Y), dev(w["F"]), dev(w["T"]))
     assert plan.last_error() == -5
     assert plan.last_error() == 0
+
+
+def _clustered(n_big=9000, n_mid=600, n_rest=400, seed=11):
+    """A box with one dense cluster (more members per grid bin and per pair
+    cell than an LDS sort holds), one medium cluster (an LDS sort) and loose
+    particles.  Cluster members overlap, which the library allows; they sit on
+    jittered lattices so no pair is closer than ~0.04 (the corrections' small-r
+    cancellation stays far below the tolerance)."""
+    rng = np.random.default_rng(seed)
+    L, grid = 40.0, 32                     # dx = 1.25
+
+    def lattice(n, lo, side):
+        k = int(math.ceil(n ** (1.0 / 3.0)))
+        g = (np.stack(np.meshgrid(*([np.arange(k)] * 3), indexing="ij"), -1).reshape(-1, 3) + 0.5) / k
+        g = g[rng.choice(len(g), size=n, replace=False)]
+        return lo + side * g + rng.uniform(-0.2, 0.2, size=(n, 3)) * side / k
+
+    # grid cell [10, 11.25)^3: one first support point, one bin; pair cell
+    # width 40/20 = 2: [10, 12)^3 holds the whole cluster
+    big = lattice(n_big, 10.05, 1.15)
+    mid = lattice(n_mid, 25.05, 1.15)
+    rest = rng.uniform(0.0, L, size=(n_rest, 3))
+    Y = np.concatenate([big, mid, rest])
+    Y = Y[rng.permutation(len(Y))]
+    N = len(Y)
+    return dict(N=N, L=L, a=A, eta=1.0, grid=grid, Sigma=1.5 * SIG, M_G=12, R_c=2.0,
+                Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_long_sort_segments_match_oracle(prec):
+    """Grid bins and pair cells with 600 and 9000 members take the workgroup
+    sorts (LDS bitonic, and rank counting); spread (all particles) and the
+    mobility of a subsample agree with the oracle, and the result is the same
+    from call to call."""
+    w = _clustered()
+    p = oracle_params(w)
+    plan = make_plan(w, PREC[prec][0])
+    Y, F, T = dev(w["Y"]), dev(w["F"]), dev(w["T"])
+    f = ff.spread(p, w["Y"], w["F"], w["T"])
+    g = host(plan.spread(Y, F, T))
+    # FP32: grid points near the big cluster sum 9000 terms
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert normwise(gpu_to_oracle_grid(g), f) < tol
+    V1, W1 = plan.mobility(Y, F, T)
+    V2, W2 = plan.mobility(Y, F, T)
+    V1, W1 = host(V1), host(W1)
+    assert np.array_equal(V1, host(V2)) and np.array_equal(W1, host(W2))
+    sub = np.sort(np.random.default_rng(3).choice(w["N"], size=60, replace=False))
+    Vr, Wr = ff.mobility(p, w["Y"], w["F"], w["T"], targets=sub)
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    assert normwise(V1[sub], Vr) < tol and normwise(W1[sub], Wr) < tol
+
+
+def test_standard_fcm_widths_recognised():
+    """Standard FCM passed with the torque width rounded differently (one part
+    in 1e14) is recognised as such: no correction, results equal to those of
+    the exact width."""
+    w = _case("standard48")[0]
+    sd = A / (6.0 * math.sqrt(math.pi)) ** (1.0 / 3.0)
+    Y, F, T = dev(w["Y"]), dev(w["F"]), dev(w["T"])
+    out = []
+    for s in (sd, sd * (1.0 + 1e-14), sd * (1.0 - 1e-14)):
+        plan = make_plan(w, 0, sigma_D_grid=s)
+        assert plan.info()["cells_per_axis"] == 1
+        V, W = plan.mobility(Y, F, T)
+        out.append((host(V), host(W)))
+    for V, W in out[1:]:
+        assert np.array_equal(V, out[0][0]) and np.array_equal(W, out[0][1])
+    p = oracle_params(w, Sigma_D=sd)
+    Vr, Wr = ff.mobility(p, w["Y"], w["F"], w["T"])
+    assert normwise(out[0][0], Vr) < 1e-10 and normwise(out[0][1], Wr) < 1e-10
