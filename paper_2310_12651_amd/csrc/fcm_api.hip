@@ -154,7 +154,6 @@ void free_plan(fcm_plan_impl* P) {
     free_events(P);
     void* bufs[] = {P->grid,  P->twid, P->counts, P->starts,    P->keys,       P->ranks,
                     P->perm,  P->scan_tmp, P->grec, P->prec,    P->ppos,       P->flag,
-                    P->seglong,
                     P->pair_hits, P->pair_count, P->corr};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -309,7 +308,6 @@ int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
     FCM_ALLOC(P->pair_hits, (size_t)3 * ncap * kPairCap * sizeof(int));
     FCM_ALLOC(P->pair_count, (size_t)3 * ncap * sizeof(int));
     FCM_ALLOC(P->corr, (size_t)6 * ncap * sizeof(double));
-    FCM_ALLOC(P->seglong, (size_t)(P->nbins + cellcap) * sizeof(int));
     FCM_ALLOC(P->flag, 16 * sizeof(int));
 #undef FCM_ALLOC
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking);
@@ -370,7 +368,7 @@ int64_t plan_bytes(int64_t ncap, int grid, int precision, int cellcap, int nbins
     b += 3 * ncap * (int64_t)(kPairCap + 1) * (int64_t)sizeof(int);
     b += 6 * ncap * (int64_t)sizeof(double);
     b += ncap * (int64_t)(grid_rec_size(precision) + sizeof(PairRec) + sizeof(double4));
-    b += (int64_t)(3 * (nbins + 1) + 3 * (cellcap + 1)) * (int64_t)sizeof(int) + 2048 * 4 + 64;
+    b += (int64_t)(2 * (nbins + 1) + 2 * (cellcap + 1)) * (int64_t)sizeof(int) + 2048 * 4 + 64;
     return b;
 }
 
@@ -398,7 +396,7 @@ int fcm_plan_footprint(int64_t N, int grid, int precision, int64_t* bytes) {
     b += N * (int64_t)(grid_rec_size(precision) + sizeof(PairRec) + sizeof(double4));
     const int64_t nbins_max = (M / 2) * (M / 2) * (M / 2);
     const int64_t cells = (int64_t)kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis;
-    b += 3 * (nbins_max + 1) * (int64_t)sizeof(int) + 3 * (cells + 1) * (int64_t)sizeof(int);
+    b += 2 * (nbins_max + 1) * (int64_t)sizeof(int) + 2 * (cells + 1) * (int64_t)sizeof(int);
     b += 4096 * (int64_t)sizeof(int);
     *bytes = b;
     return FCM_OK;

@@ -153,8 +153,7 @@ struct fcm_plan_impl {
     double* corr;          // 6N: pair + self corrections of V (3N) then Omega (3N)
     hipStream_t side;      // the pair correction runs here, beside spread and FFT
     hipEvent_t fork, join; // sorted records ready / corrections ready
-    int* seglong;          // nbins + cells: sort segments too long for one thread
-    int* flag;             // [0] = non-finite position seen, [1] = long segments listed
+    int* flag;             // [0] = non-finite position seen
     hipStream_t last_stream;
     int counts_dirty;      // counts may be non-zero (cleared by the next sort)
     // per-stage timing

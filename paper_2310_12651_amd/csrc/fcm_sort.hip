@@ -31,7 +31,6 @@ struct HashArgs {
 
 constexpr int kShortSegment = 64;      // ordered by one thread
 constexpr int kLdsSegment = 8192;      // ordered by a bitonic sort in LDS
-constexpr int kLongBlocks = 128;       // workgroups of the long-segment pass
 
 // wrap into [0, L); non-finite values, and values too large for the wrap to
 // land in [0, L), become 0 and raise the plan's flag.  Every index derived
@@ -196,9 +195,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan2_down(int* __restrict__ c
 
 __global__ void k_scatter(const int* __restrict__ keys, const int* __restrict__ ranks,
                           const int* __restrict__ start_bin, const int* __restrict__ start_cell,
-                          int* __restrict__ perm, int N, int* __restrict__ nlong) {
+                          int* __restrict__ perm, int N) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *nlong = 0;
     if (i >= N) return;
     perm[start_bin[keys[i]] + ranks[i]] = i;
     perm[N + start_cell[keys[N + i]] + ranks[N + i]] = i;
@@ -222,51 +220,47 @@ __device__ inline void segment(int s, const int* starts, int nbins, int N, int* 
 }
 
 // Order each segment of perm by value and record the inverse permutation
-// inv[perm[j]] = j.  A thread orders a short segment by insertion; longer
-// segments are listed for k_segment_order_long.
-__global__ void k_segment_order(const int* __restrict__ starts, int nbins, int nseg, int N,
-                                int* __restrict__ perm, int* __restrict__ inv,
-                                int* __restrict__ longlist, int* __restrict__ nlong) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nseg) return;
-    int b, e;
-    int *pm, *iv;
-    segment(s, starts, nbins, N, perm, inv, &b, &e, &pm, &iv);
-    if (e - b > kShortSegment) {
-        longlist[atomicAdd(nlong, 1)] = s;
-        return;
-    }
-    for (int i = b + 1; i < e; ++i) {
-        const int v = pm[i];
-        int j = i - 1;
-        while (j >= b && pm[j] > v) {
-            pm[j + 1] = pm[j];
-            --j;
-        }
-        pm[j + 1] = v;
-    }
-    for (int i = b; i < e; ++i) iv[pm[i]] = i;
-}
-
-// The listed long segments, one workgroup each (blocks stride over the list,
-// whose length is fixed by the previous launch).  Up to kLdsSegment members:
-// bitonic sort in LDS.  Beyond: every member's rank is the number of smaller
-// members, counted against copies of the segment staged through LDS (tmp
-// holds the copy, indexed like perm).
-__global__ __launch_bounds__(256) void k_segment_order_long(const int* __restrict__ starts,
-                                                            int nbins, int N, int* __restrict__ perm,
-                                                            int* __restrict__ inv,
-                                                            const int* __restrict__ longlist,
-                                                            const int* __restrict__ nlong,
-                                                            int* __restrict__ tmp) {
+// inv[perm[j]] = j.  A thread orders a short segment by insertion.  Longer
+// segments of the block's range are then ordered by the whole workgroup, one
+// after the other: up to kLdsSegment members by a bitonic sort in LDS, beyond
+// that by rank counting (a member's rank is the number of smaller members,
+// counted against a copy of the segment staged through LDS; tmp holds the
+// copy, indexed like perm).
+__global__ __launch_bounds__(256) void k_segment_order(const int* __restrict__ starts, int nbins,
+                                                       int nseg, int N, int* __restrict__ perm,
+                                                       int* __restrict__ inv, int* __restrict__ tmp) {
     __shared__ int sh[kLdsSegment];
-    const int count = *nlong;
+    __shared__ int nlong;
+    __shared__ int longs[256];
     const int t = threadIdx.x, nt = blockDim.x;
-    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+    if (t == 0) nlong = 0;
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + t;
+    if (s < nseg) {
         int b, e;
         int *pm, *iv;
-        const int s = longlist[q];
         segment(s, starts, nbins, N, perm, inv, &b, &e, &pm, &iv);
+        if (e - b > kShortSegment) {
+            longs[atomicAdd(&nlong, 1)] = s;
+        } else {
+            for (int i = b + 1; i < e; ++i) {
+                const int v = pm[i];
+                int j = i - 1;
+                while (j >= b && pm[j] > v) {
+                    pm[j + 1] = pm[j];
+                    --j;
+                }
+                pm[j + 1] = v;
+            }
+            for (int i = b; i < e; ++i) iv[pm[i]] = i;
+        }
+    }
+    __syncthreads();
+    const int count = nlong;
+    for (int q = 0; q < count; ++q) {
+        int b, e;
+        int *pm, *iv;
+        segment(longs[q], starts, nbins, N, perm, inv, &b, &e, &pm, &iv);
         const int n = e - b;
         if (n <= kLdsSegment) {
             int p2 = 1;
@@ -415,18 +409,16 @@ hipError_t launch_scatter(const fcm_plan_impl* P, hipStream_t st) {
     int N = (int)P->N;
     const int* sb = P->starts;
     const int* sc = P->starts + P->nbins + 1;
-    int* nlong = P->flag + 1;
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(N, 256)), dim3(256), 0, st, P->keys, P->ranks, sb,
-                       sc, P->perm, N, nlong);
+                       sc, P->perm, N);
     // The ranks are dead after the scatter: their buffer takes the inverse
     // permutation.  Without a pair search the pair order is the identity, which
-    // the hash already wrote there.
+    // the hash already wrote there.  pair_hits is free until the pair pass
+    // (which runs after the records are built): it holds the copies of the
+    // longest segments.
     const int nseg = P->nbins + (P->rc > 0.0 ? P->ncells : 0);
     hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, P->starts,
-                       P->nbins, nseg, N, P->perm, P->ranks, P->seglong, nlong);
-    // pair_hits is free until the pair pass (which runs after the records are built)
-    hipLaunchKernelGGL(k_segment_order_long, dim3(kLongBlocks), dim3(256), 0, st, P->starts, P->nbins,
-                       N, P->perm, P->ranks, P->seglong, nlong, P->pair_hits);
+                       P->nbins, nseg, N, P->perm, P->ranks, P->pair_hits);
     return hipGetLastError();
 }
 
