@@ -14,6 +14,10 @@ continuous-batching FP32-bulk server (p50/p99 latency, throughput).
 
     python bench.py [--steps K] [--warmup W] [--workload dense|dilute|rods|small|serving]
                     [--no-cpu] [--no-fp64] [--no-serving] [--requests R]
+    python bench.py --compare-standard [--compare-al A,..] [--compare-phi P,..]
+
+The second form prints the fast-against-standard FCM comparison of Sec. 5.3 instead
+(evaluations/s ratio over volume fraction and a/L, and the crossover fraction).
 """
 
 import argparse
