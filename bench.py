@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--compare-al", default="0.002,0.004,0.008,0.012")
     ap.add_argument("--compare-phi", default="0.005,0.01,0.02,0.04,0.08,0.12,0.16,0.20,0.25,0.30")
     ap.add_argument("--compare-steps", type=int, default=10)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="instead of the headline run: the library's error calibration "
+                         "(Tables 1-2 of Sec. 5.1) on the FP64 path at N = 64457, phi = 8 %%, a/L = 1/150")
     ap.add_argument("--copy-calib", action="store_true",
                     help="before timing, copy a field-sized device buffer 3 times (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -76,7 +79,7 @@ def algorithmic_bytes(w, stage):
 
 KERNEL_OF_STAGE = {"spread": "k_spread", "fft_x_fwd": "k_fft_x_r2c_reg", "fft_y_fwd": "k_fft_y_reg",
                    "fft_z_solve": "k_fft_z_solve_reg", "fft_y_inv": "k_fft_y_reg",
-                   "fft_x_inv": "k_fft_x_c2r_reg", "interp": "k_interp4", "pair": "k_pair_eval",
+                   "fft_x_inv": "k_fft_x_c2r_reg", "interp": "k_interp8", "pair": "k_pair_eval",
                    "sort": "k_hash"}
 SOURCE_OF_STAGE = {"spread": "fcm_grid.hip", "interp": "fcm_grid.hip", "pair": "fcm_pair.hip",
                    "sort": "fcm_sort.hip"}
@@ -331,6 +334,109 @@ def compare_standard(args, torch):
                               "phi_c ~ -9.24 a/L + 0.22")
 
 
+def calibrate(args, torch):
+    """The error calibration of Sec. 5.1 redone for this library (FP64 path,
+    force only, eps = mean_n |V_n - U_n| / |U_n|), in the paper's setting: a
+    suspension at phi = 8 % in a box with a/L = 1/150 (N = 64457).  U is fast
+    FCM with every error far below 1e-8 (Sigma/dx = 1.6, M_G = 24, R_c = 12
+    Sigma).  Table 1: eps over Sigma/dx and M_G with all pairs within 12 Sigma
+    corrected (Sigma ~ 2 sigma); per tolerance, the smallest Sigma/dx whose
+    best error over M_G reaches it, and there the smallest M_G that does.
+    Table 2: eps over Sigma/sigma and R_c = lambda Sigma with the grid resolved
+    (Sigma/dx = 1.6, M_G = 24) at phi = 4, 8, 16, 32 %; per tolerance the
+    smallest lambda (interpolated in log eps) that reaches it, per Sigma and
+    the largest over Sigma.  Positions: the jittered lattice of the request
+    stream; F ~ N(0, 1)."""
+    import numpy as np
+
+    import workloads
+    from paper_2310_12651_amd import FCM_FP64, Plan
+    a, sigma, L = 1.0, 1.0 / math.sqrt(math.pi), 150.0
+    tols = (1e-2, 1e-3, 1e-4, 1e-6, 1e-8)
+
+    def grid_for(ratio, Sigma0):
+        M = workloads.smooth_grid(int(math.ceil(L * ratio / Sigma0 - 1e-9)))
+        return M, ratio * L / M
+
+    def velocities(Y, F, N, Sigma, M, MG, R_c):
+        plan = Plan(N, L, a, Sigma, M, R_c, support=MG, precision=FCM_FP64)
+        V, _ = plan.mobility(Y, F, None, want_omega=False)
+        torch.cuda.synchronize()
+        plan.close()
+        return V.cpu().numpy()
+
+    def eps(V, U):
+        return float(np.mean(np.linalg.norm(V - U, axis=1) / np.linalg.norm(U, axis=1)))
+
+    def suspension(phi, seed):
+        N = int(round(phi * L ** 3 / (4.0 * math.pi * a ** 3 / 3.0)))
+        rng = np.random.default_rng(workloads.SEED_BASE + seed)
+        Yh = workloads.lattice_positions(N, L, a, rng)
+        return N, torch.as_tensor(Yh, device="cuda"), torch.as_tensor(rng.normal(size=(N, 3)), device="cuda")
+
+    def first_below(xs, es, tol):
+        """Smallest x reaching tol, interpolated in log eps between neighbours."""
+        for k, (x, e) in enumerate(zip(xs, es)):
+            if e <= tol:
+                if k == 0:
+                    return x
+                x0, e0 = xs[k - 1], es[k - 1]
+                t = (math.log(e0) - math.log(tol)) / (math.log(e0) - math.log(e))
+                return x0 + t * (x - x0)
+        return None
+
+    # Table 1
+    N, Y, F = suspension(0.08, 3000)
+    M, S = grid_for(1.6, 2.0 * sigma)
+    U = velocities(Y, F, N, S, M, 24, 12.0 * S)
+    ratios = [round(0.6 + 0.05 * k, 2) for k in range(21)]
+    mgs = list(range(6, 21))
+    t1 = {}
+    for r in ratios:
+        M, S = grid_for(r, 2.0 * sigma)
+        for MG in mgs:
+            if MG <= M:
+                t1[(r, MG)] = eps(velocities(Y, F, N, S, M, MG, 12.0 * S), U)
+        log(f"[calibrate] table 1: Sigma/dx={r} grid {M}: " +
+            " ".join(f"{MG}:{t1[(r, MG)]:.1e}" for MG in mgs if (r, MG) in t1))
+    table1 = []
+    for tol in tols:
+        floor = [min(t1[(r, MG)] for MG in mgs if (r, MG) in t1) for r in ratios]
+        r = next((r for r, f in zip(ratios, floor) if f <= tol), None)
+        mg = None if r is None else next(MG for MG in mgs if (r, MG) in t1 and t1[(r, MG)] <= tol)
+        table1.append(dict(eps=tol, Sigma_over_dx=r, M_G=mg,
+                           Sigma_over_dx_interpolated=first_below(ratios, floor, tol)))
+    # Table 2
+    lams = [2.0 + 0.5 * k for k in range(17)]
+    sfacs = (1.5, 2.0, 3.0, 4.0, 5.0, 6.0)
+    table2 = {}
+    for phi in (0.04, 0.08, 0.16, 0.32):
+        N, Y, F = suspension(phi, 3100 + int(100 * phi))
+        M, S = grid_for(1.6, 1.5 * sigma)
+        U = velocities(Y, F, N, S, M, 24, 12.0 * S)
+        per = {}
+        for sf in sfacs:
+            M, S = grid_for(1.6, sf * sigma)
+            es = [eps(velocities(Y, F, N, S, M, 24, lam * S), U) for lam in lams]
+            per[sf] = es
+            log(f"[calibrate] table 2: phi={phi} Sigma/sigma={S / sigma:.2f} grid {M}: " +
+                " ".join(f"{lam:g}:{e:.1e}" for lam, e in zip(lams, es)))
+        rows = []
+        for tol in tols:
+            each = {str(sf): first_below(lams, per[sf], tol) for sf in sfacs}
+            vals = [v for v in each.values() if v is not None]
+            rows.append(dict(eps=tol, lambda_max=max(vals) if len(vals) == len(sfacs) else None,
+                             per_Sigma=each))
+        table2[str(phi)] = dict(N=N, rows=rows)
+    return dict(metric="error calibration of the FP64 path (Tables 1-2 of Sec. 5.1)",
+                table1=table1, table1_eps={f"{r},{mg}": e for (r, mg), e in t1.items()},
+                table2=table2,
+                paper_context=dict(table1=[[1e-2, 0.71, 8], [1e-3, 0.87, 9], [1e-4, 0.99, 10],
+                                           [1e-6, 1.20, 12], [1e-8, 1.39, 14]],
+                                   table2_phi8=[[1e-2, 2.47], [1e-3, 3.66], [1e-4, 5.08],
+                                                [1e-6, 7.18], [1e-8, 8.57]]))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -343,6 +449,9 @@ def main():
     import workloads
     from paper_2310_12651_amd import FCM_FP32_BULK, FCM_FP64, Plan
 
+    if args.calibrate:
+        print(json.dumps(calibrate(args, torch)), flush=True)
+        return
     if args.compare_standard:
         print(json.dumps(compare_standard(args, torch)), flush=True)
         return
