@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--calibrate", action="store_true",
                     help="instead of the headline run: the library's error calibration "
                          "(Tables 1-2 of Sec. 5.1) on the FP64 path at N = 64457, phi = 8 %%, a/L = 1/150")
+    ap.add_argument("--tune-sigma", action="store_true",
+                    help="instead of the headline run: evaluations/s against Sigma/sigma at "
+                         "a/L = 1/400 for the volume fractions of Table 3 (its optimum on this GPU)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="before timing, copy a field-sized device buffer 3 times (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -437,6 +440,60 @@ def calibrate(args, torch):
                                                 [1e-6, 7.18], [1e-8, 8.57]]))
 
 
+def tune_sigma(args, torch):
+    """Fig. 2 / Table 3 of Sec. 5.2 on this GPU: for a/L = 1/400 and the volume
+    fractions of Table 3, the evaluations/s (PTPS) of fast FCM (FP32 bulk,
+    force only) at eps = 1e-4 parameters (Sigma/dx = 1, M_G = 10, R_c = 5.5
+    Sigma) over Sigma/sigma, and the Sigma/sigma of the peak.  Grid: the
+    smallest even 2^p 3^q with dx <= Sigma (Sigma is then L / grid).
+    Positions: the jittered lattice; F ~ N(0, 1); 10 timed calls after 2."""
+    import numpy as np
+
+    import workloads
+    from paper_2310_12651_amd import FCM_FP32_BULK, Plan
+    a, sigma, L = 1.0, 1.0 / math.sqrt(math.pi), 400.0
+    facs = (1.0, 1.2, 1.4, 1.6, 1.8, 2.0, 2.3, 2.6, 3.0, 3.5, 4.0, 4.5, 5.0, 6.0, 7.0, 8.0)
+    out = []
+    for phi in (0.0005, 0.002, 0.008, 0.032, 0.128):
+        N = int(round(phi * L ** 3 / (4.0 * math.pi * a ** 3 / 3.0)))
+        rng = np.random.default_rng(workloads.SEED_BASE + 4000 + int(1e4 * phi))
+        Y = torch.as_tensor(workloads.lattice_positions(N, L, a, rng), device="cuda")
+        F = torch.as_tensor(rng.normal(size=(N, 3)), device="cuda")
+        V = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+        pts, seen = [], set()
+        for fac in facs:
+            M = workloads.smooth_grid(int(math.ceil(L / (fac * sigma) - 1e-9)))
+            if M in seen or M > 1024:
+                continue
+            seen.add(M)
+            Sig = L / M
+            if Sig < sigma:
+                continue
+            plan = Plan(N, L, a, Sig, M, 5.5 * Sig, support=10, precision=FCM_FP32_BULK)
+            for _ in range(2):
+                plan.mobility(Y, F, None, V, None, want_omega=False)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.compare_steps):
+                plan.mobility(Y, F, None, V, None, want_omega=False)
+            e1.record()
+            torch.cuda.synchronize()
+            plan.close()
+            ms = e0.elapsed_time(e1) / args.compare_steps
+            pts.append(dict(Sigma_over_sigma=Sig / sigma, grid=M, ms=ms, ptps=N / (ms * 1e-3)))
+            log(f"[tune] phi={phi} N={N} Sigma/sigma={Sig / sigma:.2f} grid {M}: {ms:.3f} ms, "
+                f"{N / (ms * 1e-3):.3g} evals/s")
+        best = max(pts, key=lambda q: q["ptps"])
+        out.append(dict(phi=phi, N=N, points=pts, optimum_Sigma_over_sigma=best["Sigma_over_sigma"],
+                        optimum_R_c_over_sigma=5.5 * best["Sigma_over_sigma"], peak_ptps=best["ptps"]))
+        del Y, F, V
+        torch.cuda.empty_cache()
+    return dict(metric="PTPS against Sigma/sigma at a/L = 1/400 (Fig. 2, Table 3), FP32 bulk",
+                rows=out, paper_context="RTX 2080 Ti: optimum Sigma/sigma 5.9, 5.1, 3.4, 1.8, 1.4 "
+                                        "for phi 0.05, 0.2, 0.8, 3.2, 12.8 %; peak ~7e6 PTPS")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -449,6 +506,9 @@ def main():
     import workloads
     from paper_2310_12651_amd import FCM_FP32_BULK, FCM_FP64, Plan
 
+    if args.tune_sigma:
+        print(json.dumps(tune_sigma(args, torch)), flush=True)
+        return
     if args.calibrate:
         print(json.dumps(calibrate(args, torch)), flush=True)
         return

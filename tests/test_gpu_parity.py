@@ -57,6 +57,14 @@ def _case(name):
         w = dict(N=N, L=L, a=A, eta=1.0, grid=36, Sigma=1.2, M_G=12, R_c=14.0,
                  Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
         return w, None
+    if name == "tiny16":
+        # grid narrower than support + tile (16 < 12 + 8): supports meet a
+        # spreading tile on both sides of the periodic seam
+        L, N = 14.0, 12
+        Y = workloads.rsa_positions(N, L, A, rng)
+        w = dict(N=N, L=L, a=A, eta=1.0, grid=16, Sigma=1.2 * L / 16, M_G=12, R_c=5.0,
+                 Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+        return w, None
     if name == "single":
         w = dict(N=1, L=16.0, a=A, eta=1.0, grid=24, Sigma=2 * SIG, M_G=12, R_c=7.5,
                  Y=np.array([[15.9, 0.01, 8.0]]), F=np.array([[1.0, -2.0, 0.5]]),
@@ -65,7 +73,7 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["small", "ragged54", "wideTorque36", "standard48", "crowded", "single"]
+CASES = ["small", "ragged54", "wideTorque36", "standard48", "crowded", "tiny16", "single"]
 PREC = {"fp64": (0, 1e-10), "fp32": (1, 1e-5)}
 
 
