@@ -540,6 +540,17 @@ def main():
         del src, dst
     plan32 = mk(FCM_FP32_BULK)
     r32 = time_path(plan32, args, Y, F, T, V, W, torch)
+    # the same positions again with the last call's sort, records and pair
+    # lists (fcm_mobility_repeat), as in repeated solves at one configuration
+    plan32.mobility(Y, F, T, V, W)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan32.mobility_repeat(F, T, V, W)
+    e1.record()
+    torch.cuda.synchronize()
+    repeat_ms = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] fp32 repeat at the same positions {repeat_ms:.3f} ms/step")
     log(f"[bench] fp32 {r32['ms_per_step']:.3f} ms/step  stages {r32['stages_ms']}")
     V32, W32 = V.cpu().numpy(), W.cpu().numpy()
     r64 = None
@@ -591,6 +602,7 @@ def main():
         "config": {"workload": w["name"], "N": N, "grid": w["grid"], "Sigma": w["Sigma"],
                    "M_G": w["M_G"], "R_c": w["R_c"], "L": w["L"], "parallelism": "single GPU"},
         "latency_ms": {"p50": r32["p50_ms"], "p99": r32["p99_ms"]},
+        "repeat_same_positions": {"ms_per_step": repeat_ms, "value": N / (repeat_ms * 1e-3)},
         "stages_ms": {k: round(v, 5) for k, v in stages.items()},
         "stage_gbs": per_stage_gbs,
         "fp64": None if r64 is None else {"value": N / (r64["ms_per_step"] * 1e-3),

@@ -110,6 +110,21 @@ int fcm_plan_destroy(fcm_plan_t p);
 int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double* T,
                  double* V, double* Omega, void* stream);
 
+/*
+ * The mobility again at the positions of this plan's last fcm_mobility call,
+ * for new forces and torques: repeated applications of M at one configuration,
+ * as in the iterative solves for the constraint forces of rigid rods (Sec. 6.1).
+ * The particle sort, the sorted positions and the pair neighbour lists of the
+ * last call are reused; only the forces and torques of the sorted records are
+ * rewritten.  Same argument conventions and results as fcm_mobility with the
+ * same pos (bitwise equal: the summation order does not change).
+ * Errors: FCM_EINVAL if F or V is NULL, or if the plan's last position-taking
+ * call was not a successful fcm_mobility (fcm_spread, fcm_interp and
+ * fcm_correct sort again and end the reuse).
+ */
+int fcm_mobility_repeat(fcm_plan_t p, const double* F, const double* T, double* V,
+                        double* Omega, void* stream);
+
 /* Stage calls: the operators of Sec. 2.1 / 3.1 / 3.4 one at a time. */
 
 /* grid_out = J~^dagger[F] + N~^dagger[T] on the grid (modified force kernel of

@@ -17,7 +17,7 @@ FCM_FP64, FCM_FP32_BULK = 0, 1
 
 EXPORTS = [
     "fcm_options_default", "fcm_plan", "fcm_plan_ex", "fcm_plan_destroy", "fcm_mobility",
-    "fcm_spread", "fcm_solve", "fcm_interp", "fcm_correct", "fcm_plan_info",
+    "fcm_mobility_repeat", "fcm_spread", "fcm_solve", "fcm_interp", "fcm_correct", "fcm_plan_info",
     "fcm_plan_footprint", "fcm_plan_last_error", "fcm_status_string", "fcm_plan_set_timing",
     "fcm_plan_stage_times",
 ]
@@ -59,6 +59,7 @@ def library():
         "fcm_plan_ex": ([ctypes.POINTER(vp), i64, cd, cd, cd, ci, cd, ctypes.POINTER(Options)], ci),
         "fcm_plan_destroy": ([vp], ci),
         "fcm_mobility": ([vp, dp, dp, dp, dp, dp, vp], ci),
+        "fcm_mobility_repeat": ([vp, dp, dp, dp, dp, vp], ci),
         "fcm_spread": ([vp, dp, dp, dp, vp, vp], ci),
         "fcm_solve": ([vp, vp, vp], ci),
         "fcm_interp": ([vp, dp, vp, dp, dp, vp], ci),
@@ -180,6 +181,21 @@ class Plan:
                                       _ptr(T, "T", N, f64, True), _ptr(V, "V", N, f64),
                                       _ptr(Omega, "Omega", N, f64, True), _stream(stream)),
                "fcm_mobility")
+        return V, Omega
+
+    def mobility_repeat(self, F, T=None, V=None, Omega=None, stream=None, want_omega=True):
+        """fcm_mobility_repeat: the mobility at the positions of the last mobility call."""
+        import torch
+        N = self.N
+        if V is None:
+            V = torch.empty((N, 3), dtype=torch.float64, device=F.device)
+        if Omega is None and want_omega:
+            Omega = torch.empty((N, 3), dtype=torch.float64, device=F.device)
+        f64 = torch.float64
+        _check(library().fcm_mobility_repeat(self.handle, _ptr(F, "F", N, f64),
+                                             _ptr(T, "T", N, f64, True), _ptr(V, "V", N, f64),
+                                             _ptr(Omega, "Omega", N, f64, True), _stream(stream)),
+               "fcm_mobility_repeat")
         return V, Omega
 
     def spread(self, pos, F, T=None, grid_out=None, stream=None):

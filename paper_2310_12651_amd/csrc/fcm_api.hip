@@ -174,6 +174,7 @@ int map_err(hipError_t e) {
 // they are cleared here first.
 hipError_t sort_particles(fcm_plan_impl* P, const double* pos, hipStream_t st) {
     hipError_t e;
+    P->repeat_ok = 0;
     if (P->counts_dirty &&
         (e = launch_fill(P->counts, P->nbins + P->cells_cap, 0, st)) != hipSuccess)
         return e;
@@ -341,6 +342,7 @@ int plan_rebind(fcm_plan_impl* P, const fcm_plan_impl* d) {
     if (d->M != P->M || d->MG != P->MG || d->precision != P->precision || d->kahan != P->kahan ||
         d->N > P->Ncap || d->ncells > P->cells_cap)
         return FCM_EINVAL;
+    P->repeat_ok = 0;
     P->N = d->N;
     P->L = d->L;
     P->a = d->a;
@@ -443,6 +445,43 @@ int fcm_plan_info(fcm_plan_t p, int64_t* N, int* grid, int* support, int* precis
     return FCM_OK;
 }
 
+namespace {
+
+// The mobility after the records are in place (from a new sort, or refreshed
+// forces at the last sort's positions): pair correction on the side stream
+// (with a fresh neighbour search when `scan`), spread, solve, interpolation.
+hipError_t mobility_from_records(fcm_plan_impl* p, const double* T, double* V, double* Omega,
+                                 hipStream_t st, hipEvent_t* ev, bool scan) {
+    const bool corr = needs_correction(p);
+    hipError_t e = hipSuccess;
+    // The pair correction depends only on the sorted records: it runs on the
+    // plan's side stream while spread and FFT run here, into the plan's
+    // correction buffer, which the interpolation adds to its results.
+    if (corr) {
+        e = hipEventRecord(p->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
+        if (ev && e == hipSuccess) (void)hipEventRecord(ev[10], p->side);
+        if (e == hipSuccess)
+            e = launch_pair(p, p->corr, Omega ? p->corr + 3 * p->N : nullptr, T != nullptr, p->side,
+                            true, scan);
+        if (ev && e == hipSuccess) (void)hipEventRecord(ev[11], p->side);
+        if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
+    } else if (ev) {
+        (void)hipEventRecord(ev[10], st);
+        (void)hipEventRecord(ev[11], st);
+    }
+    // the field stays inside the call, so spread, solve and interpolation may
+    // pass it along in the tiled layout
+    const bool tiled = solve_tiles(p);
+    if (e == hipSuccess) e = launch_spread(p, T != nullptr, p->grid, st, tiled);
+    if (e == hipSuccess) e = launch_solve(p, p->grid, st, ev ? ev + 2 : nullptr, tiled);
+    if (e == hipSuccess && corr) e = hipStreamWaitEvent(st, p->join, 0);
+    if (e == hipSuccess) e = launch_interp(p, p->grid, V, Omega, st, tiled, corr ? p->corr : nullptr);
+    return e;
+}
+
+}  // namespace
+
 int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double* T, double* V,
                  double* Omega, void* stream) {
     if (!p || !pos || !F || !V) return FCM_EINVAL;
@@ -459,31 +498,35 @@ int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double*
     if (e == hipSuccess)
         e = corr ? launch_gather_both(p, pos, F, T, st) : launch_gather_grid(p, pos, F, T, st);
     mark(1);
-    // The pair correction depends only on the sorted records: it runs on the
-    // plan's side stream while spread and FFT run here, into the plan's
-    // correction buffer, which the interpolation adds to its results.
-    if (e == hipSuccess && corr) {
-        e = hipEventRecord(p->fork, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
-        if (ev && e == hipSuccess) (void)hipEventRecord(ev[10], p->side);
-        if (e == hipSuccess)
-            e = launch_pair(p, p->corr, Omega ? p->corr + 3 * p->N : nullptr, T != nullptr, p->side,
-                            true);
-        if (ev && e == hipSuccess) (void)hipEventRecord(ev[11], p->side);
-        if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
-    } else if (ev) {
-        (void)hipEventRecord(ev[10], st);
-        (void)hipEventRecord(ev[11], st);
-    }
-    // the field stays inside the call, so spread, solve and interpolation may
-    // pass it along in the tiled layout
-    const bool tiled = solve_tiles(p);
-    if (e == hipSuccess) e = launch_spread(p, T != nullptr, p->grid, st, tiled);
-    if (e == hipSuccess) e = launch_solve(p, p->grid, st, ev ? ev + 2 : nullptr, tiled);
-    if (e == hipSuccess && corr) e = hipStreamWaitEvent(st, p->join, 0);
-    if (e == hipSuccess) e = launch_interp(p, p->grid, V, Omega, st, tiled, corr ? p->corr : nullptr);
+    if (e == hipSuccess) e = mobility_from_records(p, T, V, Omega, st, ev, true);
     mark(8);
     mark(9);
+    // the records (and the pair lists) now describe these positions
+    if (e == hipSuccess) p->repeat_ok = 1;
+    return map_err(e);
+}
+
+int fcm_mobility_repeat(fcm_plan_t p, const double* F, const double* T, double* V, double* Omega,
+                        void* stream) {
+    if (!p || !F || !V) return FCM_EINVAL;
+    if (!p->repeat_ok) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    hipEvent_t* ev = call_events(p);
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    const bool corr = needs_correction(p);
+    // The pair records are read by the previous call's correction on the side
+    // stream until its join, which this stream has already waited for.
+    hipError_t e = launch_refresh_forces(p, F, T, corr, st);
+    mark(1);
+    if (e == hipSuccess) e = mobility_from_records(p, T, V, Omega, st, ev, false);
+    mark(8);
+    mark(9);
+    if (e != hipSuccess) p->repeat_ok = 0;
     return map_err(e);
 }
 

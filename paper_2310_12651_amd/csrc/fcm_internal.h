@@ -156,6 +156,8 @@ struct fcm_plan_impl {
     int* flag;             // [0] = non-finite position seen
     hipStream_t last_stream;
     int counts_dirty;      // counts may be non-zero (cleared by the next sort)
+    int repeat_ok;         // the sorted records and pair lists belong to the last
+                           // fcm_mobility's positions (fcm_mobility_repeat may run)
     // per-stage timing
     int timing;
     int ev_calls;           // calls recorded
@@ -182,6 +184,10 @@ hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const d
 // both of the above in one launch
 hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const double* F,
                               const double* T, hipStream_t st);
+// new forces and torques into the records of the last sort (grid records, and
+// pair records when `pair`); T may be null (zero torques)
+hipError_t launch_refresh_forces(const fcm_plan_impl* P, const double* F, const double* T,
+                                 bool pair, hipStream_t st);
 
 // tiled: write the field in the x-y tiled layout of launch_solve
 hipError_t launch_spread(const fcm_plan_impl* P, bool torque, void* grid, hipStream_t st,
@@ -197,9 +203,10 @@ hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, do
 hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st,
                         hipEvent_t* ev = nullptr, bool tiled = false);
 bool solve_tiles(const fcm_plan_impl* P);
-// store: write the corrections to V and W (else add them)
+// store: write the corrections to V and W (else add them); scan: search the
+// neighbours first (else reuse the lists of the last search, same positions)
 hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool torque,
-                       hipStream_t st, bool store = false);
+                       hipStream_t st, bool store = false, bool scan = true);
 
 // plan construction pieces (fcm_api.hip), shared with the request server
 int fft_maxe(int precision, bool zpass);

@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restr
 }  // namespace
 
 hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torque*/,
-                       hipStream_t st, bool store) {
+                       hipStream_t st, bool store, bool scan) {
     PairArgs a;
     a.N = (int)P->N;
     a.m = P->m;
@@ -369,7 +369,7 @@ hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torq
     a.with_pairs = P->rc > 0.0 ? 1 : 0;
     a.store = store ? 1 : 0;
     const int* cs = P->starts + P->nbins + 1;
-    if (a.with_pairs)
+    if (a.with_pairs && scan)
         hipLaunchKernelGGL(k_pair_scan, dim3((3 * a.N + kScanBlock - 1) / kScanBlock), dim3(kScanBlock),
                            0, st, P->ppos, P->prec, cs, a, P->pair_hits, P->pair_count);
     // width constants of the six Gaussians (see correction_coeffs)

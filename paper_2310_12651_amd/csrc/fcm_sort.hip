@@ -445,6 +445,37 @@ hipError_t place(const fcm_plan_impl* P, const double* pos, const double* F, con
     return hipGetLastError();
 }
 
+// New forces and torques for the records of the last sort: thread i reads
+// particle i (coalesced) and rewrites the force and torque fields of its grid
+// record (and pair record) in place; positions, supports and cells stay.
+template <typename R>
+__global__ void k_refresh(const double* __restrict__ F, const double* __restrict__ T,
+                          const int* __restrict__ inv, int N, double normF, double normT,
+                          GridRec<R>* __restrict__ grec, PairRec* __restrict__ prec) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double f[3], t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        f[a] = F[3 * (int64_t)i + a];
+        t[a] = T ? T[3 * (int64_t)i + a] : 0.0;
+    }
+    GridRec<R>& g = grec[inv[i]];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.F[a] = (R)(f[a] * normF);
+        g.T[a] = (R)(t[a] * normT);
+    }
+    if (prec) {
+        PairRec& r = prec[inv[N + i]];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r.F[a] = f[a];
+            r.T[a] = t[a];
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_gather_grid(const fcm_plan_impl* P, const double* pos, const double* F,
@@ -460,6 +491,24 @@ hipError_t launch_gather_pair(const fcm_plan_impl* P, const double* pos, const d
 hipError_t launch_gather_both(const fcm_plan_impl* P, const double* pos, const double* F,
                               const double* T, hipStream_t st) {
     return place(P, pos, F, T, true, true, st);
+}
+
+hipError_t launch_refresh_forces(const fcm_plan_impl* P, const double* F, const double* T,
+                                 bool pair, hipStream_t st) {
+    const int N = (int)P->N;
+    const double pi = 3.14159265358979323846;
+    const double normF = pow(2.0 * pi * P->Sigma * P->Sigma, -1.5);
+    const double normT =
+        pow(2.0 * pi * P->SigmaD * P->SigmaD, -1.5) / (2.0 * P->SigmaD * P->SigmaD);
+    const dim3 g(blocks_for(N, 256)), b(256);
+    PairRec* pr = pair ? P->prec : nullptr;
+    if (P->precision == FCM_FP64)
+        hipLaunchKernelGGL(k_refresh<double>, g, b, 0, st, F, T, P->ranks, N, normF, normT,
+                           (GridRec<double>*)P->grec, pr);
+    else
+        hipLaunchKernelGGL(k_refresh<float>, g, b, 0, st, F, T, P->ranks, N, normF, normT,
+                           (GridRec<float>*)P->grec, pr);
+    return hipGetLastError();
 }
 
 }  // namespace fcm

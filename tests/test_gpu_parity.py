@@ -270,3 +270,34 @@ def test_standard_fcm_widths_recognised():
     p = oracle_params(w, Sigma_D=sd)
     Vr, Wr = ff.mobility(p, w["Y"], w["F"], w["T"])
     assert normwise(out[0][0], Vr) < 1e-10 and normwise(out[0][1], Wr) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mobility_repeat_equals_full_call(prec):
+    """fcm_mobility_repeat reuses the last call's sort, records and pair lists:
+    for new forces and torques it returns exactly what fcm_mobility returns at
+    the same positions (also without torques or Omega), and it is refused
+    once another call has sorted other positions."""
+    w = _case("crowded")[0]
+    plan = make_plan(w, PREC[prec][0])
+    rng = np.random.default_rng(21)
+    Y = dev(w["Y"])
+    F1, T1 = dev(w["F"]), dev(w["T"])
+    F2, T2 = dev(rng.normal(size=(w["N"], 3))), dev(rng.normal(size=(w["N"], 3)))
+    plan.mobility(Y, F1, T1)
+    Vr, Wr = plan.mobility_repeat(F2, T2)
+    Vr, Wr = host(Vr), host(Wr)
+    V0r, _ = plan.mobility_repeat(F2, None, want_omega=False)
+    V0r = host(V0r)
+    Vf, Wf = plan.mobility(Y, F2, T2)
+    assert np.array_equal(Vr, host(Vf)) and np.array_equal(Wr, host(Wf))
+    V0f, _ = plan.mobility(Y, F2, None, want_omega=False)
+    assert np.array_equal(V0r, host(V0f))
+    # and against the oracle at the same positions
+    Vo, Wo = ff.mobility(oracle_params(w), w["Y"], host(F2), host(T2))
+    assert normwise(Vr, Vo) < PREC[prec][1] and normwise(Wr, Wo) < PREC[prec][1]
+    # a stage call sorts again: the reuse ends
+    plan.interp(Y, plan.new_grid().zero_())
+    from paper_2310_12651_amd import FCMError
+    with pytest.raises(FCMError):
+        plan.mobility_repeat(F2, T2)
