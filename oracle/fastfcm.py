@@ -39,9 +39,13 @@ from . import closed_forms as cf
 class Params:
     """Fast-FCM parameters (Sec. 5): box L, grid M per axis, support M_G,
     particle radius a, modified widths Sigma (force) and Sigma_D (torque,
-    Sec. 3.4; the paper takes Sigma_D = Sigma), cut-off R_c, viscosity eta."""
-    L: float
-    M: int
+    Sec. 3.4; the paper takes Sigma_D = Sigma), cut-off R_c, viscosity eta.
+
+    L and M are one number each for a cube, or three (x, y, z) for a
+    rectangular box; the grid spacing L / M must then be the same on all axes.
+    """
+    L: object
+    M: object
     a: float
     Sigma: float
     M_G: int
@@ -52,6 +56,16 @@ class Params:
     def __post_init__(self):
         if self.Sigma_D is None:
             self.Sigma_D = self.Sigma
+        Lv = np.broadcast_to(np.asarray(self.L, dtype=np.float64), (3,)).copy()
+        Mv = np.broadcast_to(np.asarray(self.M, dtype=np.int64), (3,)).copy()
+        h = Lv / Mv
+        if np.max(np.abs(h - h[0])) > 1e-12 * h[0]:
+            raise ValueError("the grid spacing L/M must be the same on all axes")
+        self.Lv, self.Mv = Lv, tuple(int(m) for m in Mv)
+
+    @property
+    def cubic(self):
+        return self.Mv[0] == self.Mv[1] == self.Mv[2]
 
     @property
     def sigma(self):
@@ -65,35 +79,42 @@ class Params:
 
     @property
     def dx(self):
-        return self.L / self.M
+        return float(self.Lv[0] / self.Mv[0])
 
 
 # --- Sec. 4, steps 1-2: spatial hashing and cell lists ---------------------
 
 def wrap(Y, L):
-    """Map positions into the periodic box [0, L)."""
+    """Map positions into the periodic box [0, L) (L one side, or three)."""
+    L = np.asarray(L, dtype=np.float64)
     Yw = np.mod(np.asarray(Y, dtype=np.float64), L)
-    Yw[Yw >= L] = 0.0
+    Yw[Yw >= np.broadcast_to(L, Yw.shape)] = 0.0
     return Yw
 
 
 def cell_counts(L, R_c):
-    """Cells per direction m = max(int(L / R_c), 3) (Sec. 4, spatial hashing)."""
-    return max(int(L / R_c), 3)
+    """Cells per direction m = max(int(L / R_c), 3) (Sec. 4, spatial hashing),
+    per axis when L has three sides."""
+    Lv = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    m = np.array([max(int(l / R_c), 3) for l in Lv], dtype=np.int64)
+    return int(m[0]) if np.ndim(L) == 0 else m
 
 
 def hash_particles(Y, L, m):
     """Cell index x_c + (y_c + z_c m_y) m_x of every particle (Sec. 4)."""
-    c = np.floor(wrap(Y, L) / (L / m)).astype(np.int64)
-    c = np.minimum(c, m - 1)
-    return c[:, 0] + (c[:, 1] + c[:, 2] * m) * m
+    Lv = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    mv = np.broadcast_to(np.asarray(m, dtype=np.int64), (3,))
+    c = np.floor(wrap(Y, Lv) / (Lv / mv)).astype(np.int64)
+    c = np.minimum(c, mv - 1)
+    return c[:, 0] + (c[:, 1] + c[:, 2] * mv[1]) * mv[0]
 
 
 def cell_lists(keys, m):
     """Sort by key (stable) and return (order, start) with start[c]..start[c+1]
     the sorted positions of the particles in cell c (Sec. 4, sorting)."""
+    ncell = int(np.prod(np.broadcast_to(np.asarray(m, dtype=np.int64), (3,))))
     order = np.argsort(keys, kind="stable")
-    start = np.searchsorted(keys[order], np.arange(m ** 3 + 1))
+    start = np.searchsorted(keys[order], np.arange(ncell + 1))
     return order, start
 
 
@@ -111,12 +132,12 @@ def _particle_weights(p, Yw):
     """For a block of particles: flat grid indices and, at every support point,
     the modified force kernel Delta~(d; Sigma) (Sec. 3, definition of Delta~)
     and the torque factor Delta(d; Sigma_D) / (2 Sigma_D^2) with d itself."""
-    M, MG = p.M, p.M_G
-    ix, dxs = _window(Yw[:, 0], p.dx, MG, M)
-    iy, dys = _window(Yw[:, 1], p.dx, MG, M)
-    iz, dzs = _window(Yw[:, 2], p.dx, MG, M)
+    (Mx, My, Mz), MG = p.Mv, p.M_G
+    ix, dxs = _window(Yw[:, 0], p.dx, MG, Mx)
+    iy, dys = _window(Yw[:, 1], p.dx, MG, My)
+    iz, dzs = _window(Yw[:, 2], p.dx, MG, Mz)
     # full 3-D support, shape (n, MG, MG, MG), axis order (x, y, z)
-    flat = (ix[:, :, None, None] * M + iy[:, None, :, None]) * M + iz[:, None, None, :]
+    flat = (ix[:, :, None, None] * My + iy[:, None, :, None]) * Mz + iz[:, None, None, :]
     dx3 = np.broadcast_to(dxs[:, :, None, None], flat.shape)
     dy3 = np.broadcast_to(dys[:, None, :, None], flat.shape)
     dz3 = np.broadcast_to(dzs[:, None, None, :], flat.shape)
@@ -133,11 +154,11 @@ def spread(p, Y, F, T=None, chunk=2048):
     """J~^dagger[F] + N~^dagger[T] on the grid (Sec. 3.1 eq. force_kernel_mod,
     Sec. 3.4 eq. torque_kernel_mod), truncated to M_G^3 points (Sec. 2.1).
 
-    Returns f with shape (3, M, M, M), axes (component, x, y, z).
+    Returns f with shape (3, Mx, My, Mz), axes (component, x, y, z).
     """
-    Yw = wrap(Y, p.L)
+    Yw = wrap(Y, p.Lv)
     F = np.asarray(F, dtype=np.float64)
-    M3 = p.M ** 3
+    M3 = p.Mv[0] * p.Mv[1] * p.Mv[2]
     f = np.zeros((3, M3))
     for lo in range(0, len(Yw), chunk):
         hi = min(lo + chunk, len(Yw))
@@ -154,27 +175,26 @@ def spread(p, Y, F, T=None, chunk=2048):
             comps[2] = comps[2] + dtor * (t[0] * dy3 - t[1] * dx3)
         for c in range(3):
             f[c] += np.bincount(idx, weights=comps[c].ravel(), minlength=M3)
-    return f.reshape(3, p.M, p.M, p.M)
+    return f.reshape(3, *p.Mv)
 
 
-def wavenumbers(p):
-    """Wavenumbers 2 pi j / L of numpy's FFT ordering, per axis."""
-    return 2.0 * np.pi * np.fft.fftfreq(p.M, d=1.0 / p.M) / p.L
+def wavenumbers(p, axis=0):
+    """Wavenumbers 2 pi j / L of numpy's FFT ordering along one axis."""
+    M, L = p.Mv[axis], p.Lv[axis]
+    return 2.0 * np.pi * np.fft.fftfreq(M, d=1.0 / M) / L
 
 
 def stokes_solve(p, f):
     """Inverse Stokes operator L^{-1} in Fourier space (Sec. 2.1 step 2,
     App. A): u^ = (I - k k^T / k^2) f^ / (eta k^2), u^(0) = 0.
 
-    Input and output have shape (3, M, M, M).  For even M the modes with
-    index M/2 on any axis are zeroed.
+    Input and output have shape (3, Mx, My, Mz).  Along an axis of even
+    length M the modes with index M/2 are zeroed.
     """
-    M = p.M
     fh = np.fft.fftn(f, axes=(1, 2, 3))
-    k = wavenumbers(p)
-    kx = k[:, None, None]
-    ky = k[None, :, None]
-    kz = k[None, None, :]
+    kx = wavenumbers(p, 0)[:, None, None]
+    ky = wavenumbers(p, 1)[None, :, None]
+    kz = wavenumbers(p, 2)[None, None, :]
     k2 = kx ** 2 + ky ** 2 + kz ** 2
     k2s = np.where(k2 == 0.0, 1.0, k2)
     kdotf = (kx * fh[0] + ky * fh[1] + kz * fh[2]) / k2s
@@ -183,11 +203,13 @@ def stokes_solve(p, f):
     uh[1] = (fh[1] - ky * kdotf) / (p.eta * k2s)
     uh[2] = (fh[2] - kz * kdotf) / (p.eta * k2s)
     uh[:, 0, 0, 0] = 0.0
-    if M % 2 == 0:
-        h = M // 2
-        uh[:, h, :, :] = 0.0
-        uh[:, :, h, :] = 0.0
-        uh[:, :, :, h] = 0.0
+    Mx, My, Mz = p.Mv
+    if Mx % 2 == 0:
+        uh[:, Mx // 2, :, :] = 0.0
+    if My % 2 == 0:
+        uh[:, :, My // 2, :] = 0.0
+    if Mz % 2 == 0:
+        uh[:, :, :, Mz // 2] = 0.0
     return np.real(np.fft.ifftn(uh, axes=(1, 2, 3)))
 
 
@@ -201,7 +223,7 @@ def interp(p, Y, u, want_omega=True, chunk=2048):
 
     (the second is (1/2) int (curl u) Delta after integration by parts).
     """
-    Yw = wrap(Y, p.L)
+    Yw = wrap(Y, p.Lv)
     uf = u.reshape(3, -1)
     dV = p.dx ** 3
     V = np.zeros((len(Yw), 3))
@@ -223,6 +245,7 @@ def interp(p, Y, u, want_omega=True, chunk=2048):
 # --- Sec. 4 step 6: pairwise correction, App. B: self correction -----------
 
 def min_image(x, L):
+    L = np.asarray(L, dtype=np.float64)
     return x - L * np.round(x / L)
 
 
@@ -234,7 +257,7 @@ def pair_correction(p, Y, F, T=None, targets=None):
     targets: indices of the particles whose corrections are wanted (default
     all).  Returns dV, dW of shape (len(targets), 3).
     """
-    Yw = wrap(Y, p.L)
+    Yw = wrap(Y, p.Lv)
     N = len(Yw)
     F = np.asarray(F, dtype=np.float64)
     Tq = np.zeros((N, 3)) if T is None else np.asarray(T, dtype=np.float64)
@@ -244,10 +267,10 @@ def pair_correction(p, Y, F, T=None, targets=None):
     dW = np.zeros((len(targets), 3))
     sg, sD, Sg, SD, eta = p.sigma, p.sigma_D, p.Sigma, p.Sigma_D, p.eta
     if p.R_c > 0.0:
-        m = cell_counts(p.L, p.R_c)
-        keys = hash_particles(Yw, p.L, m)
+        m = np.broadcast_to(np.asarray(cell_counts(p.Lv, p.R_c), dtype=np.int64), (3,))
+        keys = hash_particles(Yw, p.Lv, m)
         order, start = cell_lists(keys, m)
-        cw = p.L / m
+        cw = p.Lv / m
     for t, n in enumerate(targets):
         if p.R_c <= 0.0:
             dV[t] += cf.self_correction_VF(p.a, sg, Sg, eta) * F[n]
@@ -258,12 +281,12 @@ def pair_correction(p, Y, F, T=None, targets=None):
         for oz in (-1, 0, 1):
             for oy in (-1, 0, 1):
                 for ox in (-1, 0, 1):
-                    cx, cy, cz = (c[0] + ox) % m, (c[1] + oy) % m, (c[2] + oz) % m
-                    key = cx + (cy + cz * m) * m
+                    cx, cy, cz = (c[0] + ox) % m[0], (c[1] + oy) % m[1], (c[2] + oz) % m[2]
+                    key = cx + (cy + cz * m[1]) * m[0]
                     cand.append(order[start[key]:start[key + 1]])
         cand = np.concatenate(cand)
         cand = cand[cand != n]
-        x = min_image(Yw[n][None, :] - Yw[cand], p.L)
+        x = min_image(Yw[n][None, :] - Yw[cand], p.Lv)
         r = np.sqrt(np.sum(x * x, axis=1))
         sel = r < p.R_c
         cand, x = cand[sel], x[sel]
