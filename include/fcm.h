@@ -98,6 +98,19 @@ int fcm_plan(fcm_plan_t* out, int64_t N, double L, double a, double sigma_delta,
 /* As fcm_plan with options (NULL = defaults). */
 int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_delta,
                 int grid, double r_cut, const fcm_options* opt);
+/*
+ * As fcm_plan_ex for the rectangular periodic box [0, L[0]) x [0, L[1]) x
+ * [0, L[2]) (host arrays, sides along x, y, z) on a grid of grid[0] x grid[1] x
+ * grid[2] points (each an even 2^p 3^q between 8 and 1024).  The grid spacing
+ * must be the same on all axes (|L[d]/grid[d] - L[0]/grid[0]| <= 1e-12 of it);
+ * the Fourier wave numbers are 2 pi j / L[d] per axis (Sec. 2.1) and the pair
+ * cells m_d = max(int(L[d]/R_c), 3) per axis (Sec. 4).  Grid buffers of the
+ * stage calls hold 3 x grid[2] x grid[1] x grid[0] values (x fastest).
+ * Errors: as fcm_plan_ex; FCM_EINVAL also for unequal spacings or a support
+ * larger than the shortest grid axis; FCM_ERANGE if r_cut >= min(L)/2.
+ */
+int fcm_plan_box(fcm_plan_t* out, int64_t N, const double L[3], double a, double sigma_delta,
+                 const int grid[3], double r_cut, const fcm_options* opt);
 /* Release a plan and its device buffers (synchronises the device first). */
 int fcm_plan_destroy(fcm_plan_t p);
 
@@ -148,6 +161,10 @@ int fcm_correct(fcm_plan_t p, const double* pos, const double* F, const double* 
  * (Sec. 4), at most 128; 1 when R_c = 0 (no pair search). */
 int fcm_plan_info(fcm_plan_t p, int64_t* N, int* grid, int* support, int* precision,
                   int* cells_per_axis);
+/* Box sides, grid points and pair cells per axis (x, y, z) of a plan; any of
+ * the host arrays may be NULL.  For fcm_plan_info, grid and cells_per_axis are
+ * those along x. */
+int fcm_plan_box_info(fcm_plan_t p, double L[3], int grid[3], int cells[3]);
 /* Device bytes a plan with these sizes would allocate (for admission control). */
 int fcm_plan_footprint(int64_t N, int grid, int precision, int64_t* bytes);
 /* Synchronises the last call's stream and returns FCM_ENONFINITE if that call saw a

@@ -16,7 +16,8 @@ FCM_OK, FCM_EINVAL, FCM_ENOMEM, FCM_EDEVICE, FCM_ERANGE, FCM_ENONFINITE = 0, -1,
 FCM_FP64, FCM_FP32_BULK = 0, 1
 
 EXPORTS = [
-    "fcm_options_default", "fcm_plan", "fcm_plan_ex", "fcm_plan_destroy", "fcm_mobility",
+    "fcm_options_default", "fcm_plan", "fcm_plan_ex", "fcm_plan_box", "fcm_plan_box_info",
+    "fcm_plan_destroy", "fcm_mobility",
     "fcm_mobility_repeat", "fcm_spread", "fcm_solve", "fcm_interp", "fcm_correct", "fcm_plan_info",
     "fcm_plan_footprint", "fcm_plan_last_error", "fcm_status_string", "fcm_plan_set_timing",
     "fcm_plan_stage_times",
@@ -57,6 +58,9 @@ def library():
         "fcm_options_default": ([ctypes.POINTER(Options)], ci),
         "fcm_plan": ([ctypes.POINTER(vp), i64, cd, cd, cd, ci, cd], ci),
         "fcm_plan_ex": ([ctypes.POINTER(vp), i64, cd, cd, cd, ci, cd, ctypes.POINTER(Options)], ci),
+        "fcm_plan_box": ([ctypes.POINTER(vp), i64, ctypes.POINTER(cd), cd, cd, ctypes.POINTER(ci), cd,
+                          ctypes.POINTER(Options)], ci),
+        "fcm_plan_box_info": ([vp, ctypes.POINTER(cd), ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
         "fcm_plan_destroy": ([vp], ci),
         "fcm_mobility": ([vp, dp, dp, dp, dp, dp, vp], ci),
         "fcm_mobility_repeat": ([vp, dp, dp, dp, dp, vp], ci),
@@ -132,7 +136,9 @@ def fcm_plan_footprint(N, grid, precision):
 
 class Plan:
     """A fast-FCM plan: N spheres of radius a in the periodic cube [0, L)^3,
-    modified kernel width Sigma, grid^3 points, pair cut-off r_cut."""
+    modified kernel width Sigma, grid^3 points, pair cut-off r_cut.  L and grid
+    may also be three values (x, y, z) for a rectangular box with one grid
+    spacing (fcm_plan_box)."""
 
     def __init__(self, N, L, a, Sigma, grid, r_cut, eta=1.0, support=0, sigma_D_grid=0.0,
                  precision=FCM_FP32_BULK, kahan=0):
@@ -144,10 +150,21 @@ class Plan:
         o.eta, o.support, o.sigma_D_grid = float(eta), int(support), float(sigma_D_grid)
         o.precision, o.kahan = int(precision), int(kahan)
         h = ctypes.c_void_p()
-        _check(lib.fcm_plan_ex(ctypes.byref(h), int(N), float(L), float(a), float(Sigma), int(grid),
-                               float(r_cut), ctypes.byref(o)), "fcm_plan_ex")
+        if hasattr(L, "__len__") or hasattr(grid, "__len__"):
+            L3 = [float(x) for x in (L if hasattr(L, "__len__") else (L, L, L))]
+            g3 = [int(x) for x in (grid if hasattr(grid, "__len__") else (grid, grid, grid))]
+            _check(lib.fcm_plan_box(ctypes.byref(h), int(N), (ctypes.c_double * 3)(*L3), float(a),
+                                    float(Sigma), (ctypes.c_int * 3)(*g3), float(r_cut),
+                                    ctypes.byref(o)), "fcm_plan_box")
+        else:
+            L3, g3 = [float(L)] * 3, [int(grid)] * 3
+            _check(lib.fcm_plan_ex(ctypes.byref(h), int(N), float(L), float(a), float(Sigma),
+                                   int(grid), float(r_cut), ctypes.byref(o)), "fcm_plan_ex")
         self._h = h
-        self.N, self.L, self.a, self.Sigma, self.grid, self.r_cut = int(N), L, a, Sigma, int(grid), r_cut
+        self.N, self.a, self.Sigma, self.r_cut = int(N), a, Sigma, r_cut
+        self.L = L3[0] if L3[0] == L3[1] == L3[2] else tuple(L3)
+        self.grid = g3[0] if g3[0] == g3[1] == g3[2] else tuple(g3)
+        self.grid_shape = (3, g3[2], g3[1], g3[0])
         self.precision = int(precision)
         self.grid_dtype = torch.float64 if precision == FCM_FP64 else torch.float32
         info = self.info()
@@ -165,9 +182,15 @@ class Plan:
                                        ctypes.byref(p), ctypes.byref(m)), "fcm_plan_info")
         return dict(N=N.value, grid=g.value, support=s.value, precision=p.value, cells_per_axis=m.value)
 
+    def box_info(self):
+        """Box sides, grid points and pair cells per axis (x, y, z)."""
+        L, g, c = (ctypes.c_double * 3)(), (ctypes.c_int * 3)(), (ctypes.c_int * 3)()
+        _check(library().fcm_plan_box_info(self.handle, L, g, c), "fcm_plan_box_info")
+        return dict(L=tuple(L), grid=tuple(g), cells=tuple(c))
+
     def new_grid(self):
         import torch
-        return torch.empty((3, self.grid, self.grid, self.grid), dtype=self.grid_dtype, device="cuda")
+        return torch.empty(self.grid_shape, dtype=self.grid_dtype, device="cuda")
 
     def mobility(self, pos, F, T=None, V=None, Omega=None, stream=None, want_omega=True):
         import torch
@@ -253,9 +276,11 @@ class Plan:
         return library().fcm_plan_last_error(self.handle)
 
     def _check_grid(self, g):
+        n = self.grid_shape[1] * self.grid_shape[2] * self.grid_shape[3]
         if (not g.is_cuda or g.dtype != self.grid_dtype or not g.is_contiguous()
-                or g.numel() != 3 * self.grid ** 3):
-            raise ValueError(f"grid must be a contiguous device tensor of 3*{self.grid}^3 {self.grid_dtype}")
+                or g.numel() != 3 * n):
+            raise ValueError(f"grid must be a contiguous device tensor of shape {self.grid_shape}, "
+                             f"{self.grid_dtype}")
 
     def close(self):
         if self._h is not None:

@@ -81,13 +81,13 @@ int pow2_floor(int v) {
 }
 
 void choose_tiles(fcm_plan_impl* P) {
-    const int M = P->M, MG = P->MG;
+    const int M = P->M, My = P->My, Mz = P->Mz, MG = P->MG;
     double best = 1e300;
     int bx = 2, by = 2;
     for (int tx = 2; tx <= 64; ++tx) {
         if (M % tx) continue;
         for (int ty = 2; tx * ty <= 64; ++ty) {
-            if (M % ty) continue;
+            if (My % ty) continue;
             // candidate-scan work per grid point of a wavefront tile
             const double score = (double)(tx + MG - 1) * (ty + MG - 1) / (tx * ty) +
                                  (tx < 8 ? 0.01 : 0.0);
@@ -100,18 +100,18 @@ void choose_tiles(fcm_plan_impl* P) {
     }
     P->TX = bx;
     P->TY = by;
-    // tile height: a divisor of M with TZ <= M - MG + 1, so that the heights a
-    // particle's support covers within a tile form a single run
+    // tile height: a divisor of Mz with TZ <= Mz - MG + 1, so that the heights
+    // a particle's support covers within a tile form a single run
     const int tzs[] = {16, 12, 8, 6, 4, 2, 1};
     P->TZ = 1;
     for (int t : tzs)
-        if (M % t == 0 && t <= M - MG + 1) {
+        if (Mz % t == 0 && t <= Mz - MG + 1) {
             P->TZ = t;
             break;
         }
     P->nbx = M / P->TX;
-    P->nby = M / P->TY;
-    P->nbz = M / P->TZ;
+    P->nby = My / P->TY;
+    P->nbz = Mz / P->TZ;
     P->nbins = P->nbx * P->nby * P->nbz;
     auto back = [&](int T, int nb) {
         int b = (MG - 1 + T - 1) / T;
@@ -194,18 +194,26 @@ bool needs_correction(const fcm_plan_impl* P) {
 namespace fcm {
 
 // Validate the arguments and fill every scalar of a plan (no allocation).
-int plan_derive(fcm_plan_impl* P, int64_t N, double L, double a, double sigma_delta, int grid,
-                double r_cut, const fcm_options* opt_in) {
+// L and grid: box sides and grid points along x, y, z (one grid spacing).
+int plan_derive(fcm_plan_impl* P, int64_t N, const double L[3], double a, double sigma_delta,
+                const int grid[3], double r_cut, const fcm_options* opt_in) {
     memset(P, 0, sizeof(*P));  // no buffers, no events, no stream yet
     fcm_options opt;
     fcm_options_default(&opt);
     if (opt_in) opt = *opt_in;
+    if (!L || !grid) return FCM_EINVAL;
     if (N <= 0 || N > (int64_t)1 << 29) return FCM_EINVAL;
-    if (!(L > 0.0) || !isfinite(L) || !(a > 0.0) || !isfinite(a)) return FCM_EINVAL;
+    for (int d = 0; d < 3; ++d) {
+        if (!(L[d] > 0.0) || !isfinite(L[d])) return FCM_EINVAL;
+        if (!is_smooth_even(grid[d])) return FCM_EINVAL;
+    }
+    if (!(a > 0.0) || !isfinite(a)) return FCM_EINVAL;
+    const double dx = L[0] / grid[0];
+    for (int d = 1; d < 3; ++d)
+        if (fabs(L[d] / grid[d] - dx) > 1e-12 * dx) return FCM_EINVAL;
     if (!(opt.eta > 0.0) || !isfinite(opt.eta)) return FCM_EINVAL;
     if (opt.precision != FCM_FP64 && opt.precision != FCM_FP32_BULK) return FCM_EINVAL;
     if (opt.kahan < 0 || opt.kahan > 2) return FCM_EINVAL;
-    if (!is_smooth_even(grid)) return FCM_EINVAL;
     const double sigma = a / sqrt(kPi);
     const double sigmaD = a / cbrt(6.0 * sqrt(kPi));
     if (!(sigma_delta >= sigma * (1.0 - 1e-12)) || !isfinite(sigma_delta)) return FCM_EINVAL;
@@ -217,8 +225,12 @@ int plan_derive(fcm_plan_impl* P, int64_t N, double L, double a, double sigma_de
     if (!(SigmaD >= sigmaD * (1.0 - 1e-12)) || !isfinite(SigmaD)) return FCM_EINVAL;
     if (SigmaD < sigmaD * (1.0 + 1e-12)) SigmaD = sigmaD;
     if (!(r_cut >= 0.0) || !isfinite(r_cut)) return FCM_EINVAL;
-    if (r_cut >= 0.5 * L) return FCM_ERANGE;
-    const double dx = L / grid;
+    const double Lmin = fmin(L[0], fmin(L[1], L[2]));
+    if (r_cut >= 0.5 * Lmin) return FCM_ERANGE;
+    const int gmin = grid[0] < grid[1] ? (grid[0] < grid[2] ? grid[0] : grid[2])
+                                       : (grid[1] < grid[2] ? grid[1] : grid[2]);
+    const int gmax = grid[0] > grid[1] ? (grid[0] > grid[2] ? grid[0] : grid[2])
+                                       : (grid[1] > grid[2] ? grid[1] : grid[2]);
     int MG = opt.support;
     if (MG == 0) {
         const double wmax = Sigma > SigmaD ? Sigma : SigmaD;
@@ -226,14 +238,16 @@ int plan_derive(fcm_plan_impl* P, int64_t N, double L, double a, double sigma_de
         if (MG & 1) ++MG;
         if (MG < 8) MG = 8;
     }
-    if (MG < 2 || MG > kMaxSupport || MG > grid) return FCM_EINVAL;
+    if (MG < 2 || MG > kMaxSupport || MG > gmin) return FCM_EINVAL;
     // FP64 spreading stages its particles with M_G-point tables in LDS
     if (opt.precision == FCM_FP64 && MG > 24) return FCM_EINVAL;
     const int mz = fft_maxe(opt.precision, true) * 256;
-    if (grid > mz) return FCM_EINVAL;
+    if (gmax > mz) return FCM_EINVAL;
 
     P->N = N;
-    P->L = L;
+    P->L = L[0];
+    P->Ly = L[1];
+    P->Lz = L[2];
     P->a = a;
     P->eta = opt.eta;
     P->sigma = sigma;
@@ -242,28 +256,39 @@ int plan_derive(fcm_plan_impl* P, int64_t N, double L, double a, double sigma_de
     P->SigmaD = SigmaD;
     P->rc = r_cut;
     P->dx = dx;
-    P->M = grid;
-    P->H = grid / 2;
+    P->M = grid[0];
+    P->My = grid[1];
+    P->Mz = grid[2];
+    P->H = grid[0] / 2;
+    P->cubic = grid[0] == grid[1] && grid[1] == grid[2];
     P->MG = MG;
     P->precision = opt.precision;
     P->kahan = opt.kahan;
     choose_tiles(P);
-    int m = 1;                 // R_c = 0: no pair search, one cell
+    // pair cells per axis: m = max(int(L / R_c), 3) (at most kMaxCellsPerAxis);
+    // R_c = 0: no pair search, one cell
+    int mc[3] = {1, 1, 1};
     if (r_cut > 0.0) {
-        const double q = L / r_cut;
-        m = q > (double)kMaxCellsPerAxis ? kMaxCellsPerAxis : (int)q;
-        if (m < 3) m = 3;
+        for (int d = 0; d < 3; ++d) {
+            const double q = L[d] / r_cut;
+            mc[d] = q > (double)kMaxCellsPerAxis ? kMaxCellsPerAxis : (int)q;
+            if (mc[d] < 3) mc[d] = 3;
+        }
     }
-    P->m = m;
-    P->ncells = m * m * m;
-    P->radM = make_radix_plan(grid);
-    P->radH = make_radix_plan(grid / 2);
-    finish_radix_plan(P->radM, grid);
-    finish_radix_plan(P->radH, grid);
+    P->m = mc[0];
+    P->mcy = mc[1];
+    P->mcz = mc[2];
+    P->ncells = mc[0] * mc[1] * mc[2];
+    P->radH = make_radix_plan(grid[0] / 2);
+    P->radY = make_radix_plan(grid[1]);
+    P->radZ = make_radix_plan(grid[2]);
+    finish_radix_plan(P->radH, grid[0]);
+    finish_radix_plan(P->radY, grid[1]);
+    finish_radix_plan(P->radZ, grid[2]);
     const int mxy = fft_maxe(P->precision, false) * 256;
-    P->Wy = pow2_floor(mxy / grid);
+    P->Wy = pow2_floor(mxy / P->My);
     if (P->Wy > 32) P->Wy = 32;
-    P->Wz = pow2_floor(mz / grid);
+    P->Wz = pow2_floor(mz / P->Mz);
     if (P->Wz > 32) P->Wz = 32;
     P->Wx = mxy / P->H;
     if (P->Wx > 64) P->Wx = 64;
@@ -287,16 +312,16 @@ int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
     P->Ncap = ncap;
     P->cells_cap = cellcap;
     P->counts_dirty = 1;
-    const int grid = P->M;
     const size_t rs = real_size(P->precision);
-    const size_t M3 = (size_t)grid * grid * grid;
+    const size_t M3 = (size_t)P->M * P->My * P->Mz;
+    const int ntw = P->M + P->My + P->Mz;
     hipError_t e = hipSuccess;
 #define FCM_ALLOC(ptr, bytes)                                        \
     do {                                                             \
         if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes)); \
     } while (0)
     FCM_ALLOC(P->grid, 3 * M3 * rs);
-    FCM_ALLOC(P->twid, (size_t)grid * 2 * rs);
+    FCM_ALLOC(P->twid, (size_t)ntw * 2 * rs);
     FCM_ALLOC(P->counts, (size_t)(P->nbins + cellcap) * sizeof(int));
     FCM_ALLOC(P->starts, (size_t)(P->nbins + 1 + cellcap + 1) * sizeof(int));
     FCM_ALLOC(P->keys, (size_t)2 * ncap * sizeof(int));
@@ -315,20 +340,28 @@ int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->join, hipEventDisableTiming);
     if (e != hipSuccess) return map_err(e);
-    // twiddles exp(-2 pi i m / M) in extended precision, rounded once
-    const size_t n = (size_t)grid * 2;
+    // twiddles exp(-2 pi i m / n) for n = M, My, Mz in turn, in extended
+    // precision, rounded once
+    const size_t n = (size_t)ntw * 2;
     void* host = malloc(n * rs);
     if (!host) return FCM_ENOMEM;
-    for (int mm = 0; mm < grid; ++mm) {
-        const long double ang = -2.0L * 3.141592653589793238462643383279502884L * mm / grid;
-        const long double c = cosl(ang), sn = sinl(ang);
-        if (P->precision == FCM_FP64) {
-            ((double*)host)[2 * mm] = (double)c;
-            ((double*)host)[2 * mm + 1] = (double)sn;
-        } else {
-            ((float*)host)[2 * mm] = (float)c;
-            ((float*)host)[2 * mm + 1] = (float)sn;
+    const int lens[3] = {P->M, P->My, P->Mz};
+    int off = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int len = lens[d];
+        for (int mm = 0; mm < len; ++mm) {
+            const long double ang = -2.0L * 3.141592653589793238462643383279502884L * mm / len;
+            const long double c = cosl(ang), sn = sinl(ang);
+            const size_t k = (size_t)(off + mm);
+            if (P->precision == FCM_FP64) {
+                ((double*)host)[2 * k] = (double)c;
+                ((double*)host)[2 * k + 1] = (double)sn;
+            } else {
+                ((float*)host)[2 * k] = (float)c;
+                ((float*)host)[2 * k + 1] = (float)sn;
+            }
         }
+        off += len;
     }
     e = hipMemcpy(P->twid, host, n * rs, hipMemcpyHostToDevice);
     free(host);
@@ -339,12 +372,15 @@ int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
 // Re-parameterise an allocated plan with the scalars of `d` (derived for a new
 // problem of the same grid, support, precision and accumulation mode).
 int plan_rebind(fcm_plan_impl* P, const fcm_plan_impl* d) {
-    if (d->M != P->M || d->MG != P->MG || d->precision != P->precision || d->kahan != P->kahan ||
-        d->N > P->Ncap || d->ncells > P->cells_cap)
+    if (d->M != P->M || d->My != P->My || d->Mz != P->Mz || d->MG != P->MG ||
+        d->precision != P->precision || d->kahan != P->kahan || d->N > P->Ncap ||
+        d->ncells > P->cells_cap)
         return FCM_EINVAL;
     P->repeat_ok = 0;
     P->N = d->N;
     P->L = d->L;
+    P->Ly = d->Ly;
+    P->Lz = d->Lz;
     P->a = d->a;
     P->eta = d->eta;
     P->sigma = d->sigma;
@@ -354,6 +390,8 @@ int plan_rebind(fcm_plan_impl* P, const fcm_plan_impl* d) {
     P->rc = d->rc;
     P->dx = d->dx;
     P->m = d->m;
+    P->mcy = d->mcy;
+    P->mcz = d->mcz;
     P->ncells = d->ncells;
     P->selfVF = d->selfVF;
     P->selfOT = d->selfOT;
@@ -362,10 +400,10 @@ int plan_rebind(fcm_plan_impl* P, const fcm_plan_impl* d) {
 
 void plan_free(fcm_plan_impl* P) { free_plan(P); }
 
-int64_t plan_bytes(int64_t ncap, int grid, int precision, int cellcap, int nbins) {
-    const int64_t M = grid;
+int64_t plan_bytes(int64_t ncap, const int grid[3], int precision, int cellcap, int nbins) {
     const int64_t rs = (int64_t)real_size(precision);
-    int64_t b = 3 * M * M * M * rs + M * 2 * rs;
+    int64_t b = 3 * (int64_t)grid[0] * grid[1] * grid[2] * rs +
+                (int64_t)(grid[0] + grid[1] + grid[2]) * 2 * rs;
     b += 6 * ncap * (int64_t)sizeof(int);
     b += 3 * ncap * (int64_t)(kPairCap + 1) * (int64_t)sizeof(int);
     b += 6 * ncap * (int64_t)sizeof(double);
@@ -411,6 +449,13 @@ int fcm_plan(fcm_plan_t* out, int64_t N, double L, double a, double sigma_delta,
 
 int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_delta, int grid,
                 double r_cut, const fcm_options* opt_in) {
+    const double L3[3] = {L, L, L};
+    const int g3[3] = {grid, grid, grid};
+    return fcm_plan_box(out, N, L3, a, sigma_delta, g3, r_cut, opt_in);
+}
+
+int fcm_plan_box(fcm_plan_t* out, int64_t N, const double L[3], double a, double sigma_delta,
+                 const int grid[3], double r_cut, const fcm_options* opt_in) {
     if (!out) return FCM_EINVAL;
     *out = nullptr;
     fcm_plan_impl* P = new (std::nothrow) fcm_plan_impl;
@@ -442,6 +487,26 @@ int fcm_plan_info(fcm_plan_t p, int64_t* N, int* grid, int* support, int* precis
     if (support) *support = p->MG;
     if (precision) *precision = p->precision;
     if (cells_per_axis) *cells_per_axis = p->m;
+    return FCM_OK;
+}
+
+int fcm_plan_box_info(fcm_plan_t p, double L[3], int grid[3], int cells[3]) {
+    if (!p) return FCM_EINVAL;
+    if (L) {
+        L[0] = p->L;
+        L[1] = p->Ly;
+        L[2] = p->Lz;
+    }
+    if (grid) {
+        grid[0] = p->M;
+        grid[1] = p->My;
+        grid[2] = p->Mz;
+    }
+    if (cells) {
+        cells[0] = p->m;
+        cells[1] = p->mcy;
+        cells[2] = p->mcz;
+    }
     return FCM_OK;
 }
 

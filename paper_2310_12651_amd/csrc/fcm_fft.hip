@@ -260,18 +260,18 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_c2r(R* __restrict__ grid,
 }
 
 // y pass: batches of W consecutive kx columns of one (component, z) plane
+// (lines of length M = My; H = the x half-length, the number of kx columns)
 template <typename R, int DIR, int MAXE>
 __global__ __launch_bounds__(kFFTThreads) void k_fft_y(C2<R>* __restrict__ spec,
-                                                       const C2<R>* __restrict__ twg, int M,
+                                                       const C2<R>* __restrict__ twg, int M, int H,
                                                        RadixPlan rpM, int W, int lw) {
     extern __shared__ __align__(16) unsigned char smem[];
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
     C2<R>* buf = tw + M;
-    const int H = M / 2;
     const int ng = (H + W - 1) / W;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int g = blk % ng;
-    const int rest = blk / ng;  // c * M + z
+    const int rest = blk / ng;  // c * Mz + z
     const int kx0 = g * W;
     const int Wv = min(W, H - kx0);
     C2<R>* base = spec + (size_t)rest * M * H + kx0;
@@ -289,28 +289,28 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_y(C2<R>* __restrict__ spec,
 }
 
 struct ProjArgs {
-    double kunit;   // 2 pi / L
-    double scale;   // 1 / (eta M^3)
+    double kux, kuy, kuz;   // 2 pi / L along x, y, z
+    double scale;           // 1 / (eta Mx My Mz)
 };
 
 // z pass: forward FFT along z, projection / (eta k^2), inverse FFT along z
+// (lines of length M = Mz over the H x My columns (kx, ky), H = Mx / 2)
 template <typename R, int MAXE>
 __global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__ spec,
                                                              const C2<R>* __restrict__ twg, int M,
-                                                             RadixPlan rpM, int W, int lw,
-                                                             ProjArgs pa) {
+                                                             int H, int My, RadixPlan rpM, int W,
+                                                             int lw, ProjArgs pa) {
     extern __shared__ __align__(16) unsigned char smem[];
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem);
     C2<R>* buf = tw + M;  // 3 components, each M x W
-    const int H = M / 2;
     const int ng = (H + W - 1) / W;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int g = blk % ng;
     const int y = blk / ng;
     const int kx0 = g * W;
     const int Wv = min(W, H - kx0);
-    const size_t cstride = (size_t)M * M * H;
-    const size_t zstride = (size_t)M * H;
+    const size_t cstride = (size_t)M * My * H;
+    const size_t zstride = (size_t)My * H;
     C2<R>* base = spec + (size_t)y * H + kx0;
     load_twiddles(tw, twg, M);
     for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
@@ -322,18 +322,19 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) fft_lines<R, -1, MAXE>(buf + c * M * W, tw, rpM, W, lw, 1, W, true);
-    const R ku = (R)pa.kunit;
+    const R kux = (R)pa.kux, kuy = (R)pa.kuy, kuz = (R)pa.kuz;
     const R sc = (R)pa.scale;
-    const int jy = y < H ? y : y - M;
+    const int Hy = My / 2, Hz = M / 2;
+    const int jy = y < Hy ? y : y - My;
     for (int e = threadIdx.x; e < W * M; e += kFFTThreads) {
         const int w = e & (W - 1), z = e >> lw;
         const int jx = kx0 + w;
-        const int jz = z < H ? z : z - M;
-        const bool zero = (w >= Wv) || (y == H) || (z == H) || (jx == 0 && jy == 0 && jz == 0);
+        const int jz = z < Hz ? z : z - M;
+        const bool zero = (w >= Wv) || (y == Hy) || (z == Hz) || (jx == 0 && jy == 0 && jz == 0);
         C2<R> f0 = buf[e], f1 = buf[M * W + e], f2 = buf[2 * M * W + e];
         C2<R> u0 = {0, 0}, u1 = {0, 0}, u2 = {0, 0};
         if (!zero) {
-            const R kx = ku * (R)jx, ky = ku * (R)jy, kz = ku * (R)jz;
+            const R kx = kux * (R)jx, ky = kuy * (R)jy, kz = kuz * (R)jz;
             const R k2 = kx * kx + ky * ky + kz * kz;
             const R ik2 = (R)1 / k2;
             const C2<R> kf = {(kx * f0.x + ky * f1.x + kz * f2.x) * ik2,
@@ -574,16 +575,16 @@ __global__ __launch_bounds__(W * N2) void k_fft_z_solve_reg(C2<float>* __restric
 #pragma unroll
     for (int c = 0; c < 3; ++c) four_step<N1, N2, -1, 1>(v[c], tw, E + w, p, G::PL, W);
     // projection: u^ = (I - k k^T / k^2) f^ / (eta k^2 M^3); k = 0 and index-H modes -> 0
-    const float ku = (float)pa.kunit, sc = (float)pa.scale;
+    const float kux = (float)pa.kux, kuy = (float)pa.kuy, kuz = (float)pa.kuz, sc = (float)pa.scale;
     const int jx = g * W + w;
     const int jy = y < H ? y : y - M;
-    const float kx = ku * (float)jx, ky = ku * (float)jy;
+    const float kx = kux * (float)jx, ky = kuy * (float)jy;
 #pragma unroll
     for (int i = 0; i < N1; ++i) {
         const int iz = p + N2 * i;
         const int jz = iz < H ? iz : iz - M;
         const bool zero = (y == H) || (iz == H) || (jx == 0 && jy == 0 && jz == 0);
-        const float kz = ku * (float)jz;
+        const float kz = kuz * (float)jz;
         const float k2s = kx * kx + ky * ky + kz * kz;
         const float ik2 = zero ? 0.0f : 1.0f / k2s;
         const C2<float> f0 = v[0][i], f1 = v[1][i], f2 = v[2][i];
@@ -752,19 +753,23 @@ __global__ __launch_bounds__((XGeom<N1, N2>::NT)) void k_fft_x_c2r_reg(float* __
 
 
 // the z pass in LDS (all sizes and precisions)
+// twz: the twiddle table of length Mz
 template <typename R, int MZ>
-void z_lds(const fcm_plan_impl* P, C2<R>* spec, const C2<R>* tw, hipStream_t st, ProjArgs pa) {
-    const int M = P->M, H = P->H;
+void z_lds(const fcm_plan_impl* P, C2<R>* spec, const C2<R>* twz, hipStream_t st, ProjArgs pa) {
+    const int Mz = P->Mz, H = P->H;
     const int ngz = (H + P->Wz - 1) / P->Wz;
-    const size_t shz = (M + 3 * (size_t)P->Wz * M) * sizeof(C2<R>);
-    hipLaunchKernelGGL((k_fft_z_solve<R, MZ>), dim3(ngz * M), dim3(kFFTThreads), shz, st, spec, tw,
-                       M, P->radM, P->Wz, __builtin_ctz(P->Wz), pa);
+    const size_t shz = (Mz + 3 * (size_t)P->Wz * Mz) * sizeof(C2<R>);
+    hipLaunchKernelGGL((k_fft_z_solve<R, MZ>), dim3(ngz * P->My), dim3(kFFTThreads), shz, st, spec,
+                       twz, Mz, H, P->My, P->radZ, P->Wz, __builtin_ctz(P->Wz), pa);
 }
 
 ProjArgs proj_args(const fcm_plan_impl* P) {
+    const double twopi = 2.0 * 3.14159265358979323846;
     ProjArgs pa;
-    pa.kunit = 2.0 * 3.14159265358979323846 / P->L;
-    pa.scale = 1.0 / (P->eta * (double)P->M * P->M * P->M);
+    pa.kux = twopi / P->L;
+    pa.kuy = twopi / P->Ly;
+    pa.kuz = twopi / P->Lz;
+    pa.scale = 1.0 / (P->eta * (double)P->M * P->My * P->Mz);
     return pa;
 }
 
@@ -844,19 +849,22 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
 #define FCM_REG_CASE(m, a, b, c, d, e, f) \
     case m:                               \
         return solve_reg<a, b, c, d, e, f>(P, grid, st, ev, tiled);
-        switch (P->M) {
-            FCM_REG_SIZES(FCM_REG_CASE)
-            default: break;
-        }
+        if (P->cubic) switch (P->M) {
+                FCM_REG_SIZES(FCM_REG_CASE)
+                default: break;
+            }
 #undef FCM_REG_CASE
     }
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
-    const int M = P->M, H = P->H;
+    const int M = P->M, H = P->H, My = P->My, Mz = P->Mz;
+    // twiddle tables of lengths M, My, Mz, one after the other
     const C2<R>* tw = (const C2<R>*)P->twid;
+    const C2<R>* twy = tw + M;
+    const C2<R>* twz = twy + My;
     C2<R>* spec = (C2<R>*)grid;
-    const int nlines = 3 * M * M;
+    const int nlines = 3 * My * Mz;
     const size_t cs = sizeof(C2<R>);
     mark(0);
     {
@@ -866,15 +874,15 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
     }
     mark(1);
     const int ngy = (H + P->Wy - 1) / P->Wy;
-    const size_t shy = (M + (size_t)P->Wy * M) * cs;
+    const size_t shy = (My + (size_t)P->Wy * My) * cs;
     const int lwy = __builtin_ctz(P->Wy);
-    hipLaunchKernelGGL((k_fft_y<R, -1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec, tw,
-                       M, P->radM, P->Wy, lwy);
+    hipLaunchKernelGGL((k_fft_y<R, -1, MX>), dim3(ngy * 3 * Mz), dim3(kFFTThreads), shy, st, spec, twy,
+                       My, H, P->radY, P->Wy, lwy);
     mark(2);
-    z_lds<R, MZ>(P, spec, tw, st, proj_args(P));
+    z_lds<R, MZ>(P, spec, twz, st, proj_args(P));
     mark(3);
-    hipLaunchKernelGGL((k_fft_y<R, 1, MX>), dim3(ngy * 3 * M), dim3(kFFTThreads), shy, st, spec, tw, M,
-                       P->radM, P->Wy, lwy);
+    hipLaunchKernelGGL((k_fft_y<R, 1, MX>), dim3(ngy * 3 * Mz), dim3(kFFTThreads), shy, st, spec, twy,
+                       My, H, P->radY, P->Wy, lwy);
     mark(4);
     {
         const size_t shm = (M + (size_t)P->Wx * (H + 1)) * cs;
@@ -894,7 +902,7 @@ int fft_maxe(int precision, bool zpass) {
 }
 
 bool solve_tiles(const fcm_plan_impl* P) {
-    return P->precision != FCM_FP64 && reg_size(P->M) && P->M % 8 == 0;
+    return P->precision != FCM_FP64 && P->cubic && reg_size(P->M) && P->M % 8 == 0;
 }
 
 hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st, hipEvent_t* ev,

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
 
     const int lane = threadIdx.x;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int M = a.M, MG = a.MG;
+    const int Mx = a.M, My = a.My, Mz = a.Mz, MG = a.MG;
     const int btx = tile % a.nbx;
     const int rem = tile / a.nbx;
     const int bty = rem % a.nby;
@@ -169,13 +169,13 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                     if (lane < kChunk && p < end) {
                         r = rec[p];
                         int d0x = X0 - r.s[0];
-                        if (d0x < 0) d0x += M;
+                        if (d0x < 0) d0x += Mx;
                         int d0y = Y0 - r.s[1];
-                        if (d0y < 0) d0y += M;
+                        if (d0y < 0) d0y += My;
                         int d0z = Z0 - r.s[2];
-                        if (d0z < 0) d0z += M;
-                        take = (d0x < MG || d0x > M - a.TX) && (d0y < MG || d0y > M - a.TY) &&
-                               (d0z < MG || d0z > M - TZ);
+                        if (d0z < 0) d0z += Mz;
+                        take = (d0x < MG || d0x > Mx - a.TX) && (d0y < MG || d0y > My - a.TY) &&
+                               (d0z < MG || d0z > Mz - TZ);
                     }
                     const unsigned long long mask = __ballot(take);
                     const int cnt = __popcll(mask);
@@ -200,9 +200,9 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                         const int sy = __builtin_amdgcn_readfirstlane(stg.s[1][q]);
                         const int sz = __builtin_amdgcn_readfirstlane(stg.s[2][q]);
                         int dxi = gxp - sx;
-                        if (dxi < 0) dxi += M;
+                        if (dxi < 0) dxi += Mx;
                         int dyi = gyp - sy;
-                        if (dyi < 0) dyi += M;
+                        if (dyi < 0) dyi += My;
                         const bool in = lact && dxi < MG && dyi < MG;
                         const R dxv = ((R)dxi - stg.f[0][q]) * dx;
                         const R dyv = ((R)dyi - stg.f[1][q]) * dx;
@@ -236,13 +236,13 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                                 for (int c = 0; c < 3; ++c) P[c] += Pt[c];
                             }
                         }
-                        // tile heights k with (Z0 + k - sz) mod M < MG: one or
+                        // tile heights k with (Z0 + k - sz) mod Mz < MG: one or
                         // two runs, as a bit mask
                         int dz0 = Z0 - sz;
-                        if (dz0 < 0) dz0 += M;
+                        if (dz0 < 0) dz0 += Mz;
                         const int hi1 = min(TZ, MG - dz0);
-                        const int lo2 = M - dz0;
-                        const int hi2 = min(TZ, M - dz0 + MG);
+                        const int lo2 = Mz - dz0;
+                        const int hi2 = min(TZ, Mz - dz0 + MG);
                         unsigned kmask = hi1 > 0 ? low_bits(hi1) : 0u;
                         if (lo2 < TZ) kmask |= low_bits(hi2) & ~low_bits(lo2);
                         kmask = __builtin_amdgcn_readfirstlane(kmask);
@@ -283,9 +283,9 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                                 acc[2][k].add(v2);
                             }
                         };
-                        // The plan keeps TZ <= M - MG + 1, so the active heights
+                        // The plan keeps TZ <= Mz - MG + 1, so the active heights
                         // are one run and the table entry of height k is zb[k].
-                        const ZTab<R>* zb = zq + (hi1 > 0 ? dz0 : dz0 - M);
+                        const ZTab<R>* zb = zq + (hi1 > 0 ? dz0 : dz0 - Mz);
 #pragma unroll
                         for (int k = 0; k < TZ; ++k)
                             if (kmask & (1u << k)) step(k, zb[k]);
@@ -296,29 +296,29 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
         }
     }
     if (lact) {
-        const size_t M3 = (size_t)M * M * M;
-        const size_t col = a.tiled ? (size_t)((gyp >> 2) * (M << 2) + ((gxp >> 3) << 5) + ((gyp & 3) << 3) +
+        const size_t M3 = (size_t)Mx * My * Mz;
+        const size_t col = a.tiled ? (size_t)((gyp >> 2) * (Mx << 2) + ((gxp >> 3) << 5) + ((gyp & 3) << 3) +
                                               (gxp & 7))
-                                   : (size_t)gyp * M + gxp;
+                                   : (size_t)gyp * Mx + gxp;
 #pragma unroll
         for (int k = 0; k < TZ; ++k) {
-            const size_t idx = (size_t)(Z0 + k) * M * M + col;
+            const size_t idx = (size_t)(Z0 + k) * Mx * My + col;
 #pragma unroll
             for (int c = 0; c < 3; ++c) grid[c * M3 + idx] = acc[c][k].value();
         }
     }
 }
 
-// element at byte offset `col` of the M x M plane starting at `plane` (a
+// element at byte offset `col` of the plane of n values starting at `plane` (a
 // wavefront-uniform pointer)
-__device__ inline float plane_load(const float* plane, int M, unsigned col) {
+__device__ inline float plane_load(const float* plane, int n, unsigned col) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(plane), (short)0, M * M * (int)sizeof(float), kBufferWord3);
+        const_cast<float*>(plane), (short)0, n * (int)sizeof(float), kBufferWord3);
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)col, 0, 0));
 }
-__device__ inline double plane_load(const double* plane, int M, unsigned col) {
+__device__ inline double plane_load(const double* plane, int n, unsigned col) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<double*>(plane), (short)0, M * M * (int)sizeof(double), kBufferWord3);
+        const_cast<double*>(plane), (short)0, n * (int)sizeof(double), kBufferWord3);
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)col, 0, 0));
 }
 
@@ -359,7 +359,8 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
         r.f[d] = uniform(rv.f[d]);
     }
     r.orig = __builtin_amdgcn_readfirstlane(rv.orig);
-    const int M = a.M, MG = a.MG;
+    const int Mx = a.M, My = a.My, Mz = a.Mz, MG = a.MG;
+    const int nplane = Mx * My;
     const R dx = a.dx;
     if (lane < MG) {
         const R d = ((R)lane - r.f[2]) * dx;
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
         zt[wave][lane] = e;
     }
     __syncthreads();
-    const size_t M3 = (size_t)M * M * M;
+    const size_t M3 = (size_t)Mx * My * Mz;
     R v0 = 0, v1 = 0, v2 = 0, o0 = 0, o1 = 0, o2 = 0;
     const int ncol = MG * MG;
     for (int q0 = 0; q0 < ncol; q0 += 64) {
@@ -381,9 +382,9 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
         const int i = ok ? q % MG : 0;
         const int j = ok ? q / MG : 0;
         int x = r.s[0] + i;
-        if (x >= M) x -= M;
+        if (x >= Mx) x -= Mx;
         int y = r.s[1] + j;
-        if (y >= M) y -= M;
+        if (y >= My) y -= My;
         const R dxv = ((R)i - r.f[0]) * dx;
         const R dyv = ((R)j - r.f[1]) * dx;
         const R x2 = dxv * dxv, y2 = dyv * dyv;
@@ -392,17 +393,17 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
         // per-lane byte offset of the column within a z plane (32 bits); the
         // plane and component bases are wavefront-uniform
         const unsigned col =
-            (a.tiled ? (unsigned)((y >> 2) * (M << 2) + ((x >> 3) << 5) + ((y & 3) << 3) + (x & 7))
-                     : (unsigned)y * (unsigned)M + (unsigned)x) *
+            (a.tiled ? (unsigned)((y >> 2) * (Mx << 2) + ((x >> 3) << 5) + ((y & 3) << 3) + (x & 7))
+                     : (unsigned)y * (unsigned)Mx + (unsigned)x) *
             (unsigned)sizeof(R);
         for (int k = 0; k < MG; ++k) {
             int z = r.s[2] + k;
-            if (z >= M) z -= M;
+            if (z >= Mz) z -= Mz;
             const ZTab<R> e = zt[wave][k];
-            const R* pz = grid + (size_t)z * M * M;
-            const R u0 = plane_load(pz, M, col);
-            const R u1 = plane_load(pz + M3, M, col);
-            const R u2 = plane_load(pz + 2 * M3, M, col);
+            const R* pz = grid + (size_t)z * nplane;
+            const R u0 = plane_load(pz, nplane, col);
+            const R u1 = plane_load(pz + M3, nplane, col);
+            const R u2 = plane_load(pz + 2 * M3, nplane, col);
             A0[0] += e.g * u0;
             A0[1] += e.g * u1;
             A0[2] += e.g * u2;
@@ -467,9 +468,9 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
     }
 }
 
-__device__ inline float4 plane_load4(const float* plane, int M, unsigned col) {
+__device__ inline float4 plane_load4(const float* plane, int n, unsigned col) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(plane), (short)0, M * M * (int)sizeof(float), kBufferWord3);
+        const_cast<float*>(plane), (short)0, n * (int)sizeof(float), kBufferWord3);
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)col, 0, 0));
 }
 
@@ -502,7 +503,8 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
         r.f[d] = uniform(rv.f[d]);
     }
     r.orig = __builtin_amdgcn_readfirstlane(rv.orig);
-    const int M = a.M, MG = a.MG;
+    const int Mx = a.M, My = a.My, Mz = a.Mz, MG = a.MG;
+    const int nplane = Mx * My;
     const float dx = a.dx;
     if (lane < MG) {
         const float d = ((float)lane - r.f[2]) * dx;
@@ -518,10 +520,10 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
     const int j = lane >> 2, c = lane & 3;
     const int x0 = r.s[0], off0 = x0 & 3;
     int xs = (x0 - off0) + 4 * c;
-    if (xs >= M) xs -= M;
+    if (xs >= Mx) xs -= Mx;
     const bool rowok = j < MG;
     int yy = r.s[1] + (rowok ? j : 0);
-    if (yy >= M) yy -= M;
+    if (yy >= My) yy -= My;
     const float dyv = ((float)j - r.f[1]) * dx;
     const float gy = rowok ? fexp2(-dyv * dyv * a.e2) : 0.0f;
     float gw[4], gwd[4], gwd2[4];
@@ -535,24 +537,24 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
         gwd2[e] = gwd[e] * dxe;
     }
     const unsigned col =
-        (a.tiled ? (unsigned)((yy >> 2) * (M << 2) + ((xs >> 3) << 5) + ((yy & 3) << 3) + (xs & 7))
-                 : (unsigned)yy * (unsigned)M + (unsigned)xs) *
+        (a.tiled ? (unsigned)((yy >> 2) * (Mx << 2) + ((xs >> 3) << 5) + ((yy & 3) << 3) + (xs & 7))
+                 : (unsigned)yy * (unsigned)Mx + (unsigned)xs) *
         4u;
     // lanes whose row or chunk lies outside the support load nothing
     const bool need = rowok && 4 * c - off0 < MG && 4 * c + 3 - off0 >= 0;
     __syncthreads();
-    const size_t M3 = (size_t)M * M * M;
+    const size_t M3 = (size_t)Mx * My * Mz;
     float P[3] = {0, 0, 0}, Rr[3] = {0, 0, 0}, PD2[3] = {0, 0, 0}, PD[2] = {0, 0}, Q[2] = {0, 0};
     for (int k = 0; k < MG; ++k) {
         int z = r.s[2] + k;
-        if (z >= M) z -= M;
+        if (z >= Mz) z -= Mz;
         const ZTab<float> e = zt[wave][k];
-        const float* pz = grid + (size_t)z * M * M;
+        const float* pz = grid + (size_t)z * nplane;
         float4 u[3] = {make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0)};
         if (need) {
-            u[0] = plane_load4(pz, M, col);
-            u[1] = plane_load4(pz + M3, M, col);
-            u[2] = plane_load4(pz + 2 * M3, M, col);
+            u[0] = plane_load4(pz, nplane, col);
+            u[1] = plane_load4(pz + M3, nplane, col);
+            u[2] = plane_load4(pz + 2 * M3, nplane, col);
         }
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
@@ -630,7 +632,7 @@ __global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restric
     __shared__ int origs[4][kSlots];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int M = a.M, MG = a.MG;
+    const int Mx = a.M, My = a.My, Mz = a.Mz, MG = a.MG;
     const int ppw = min(kSlots, 32 / MG);
     const int h = lane >> 5, r = lane & 31;
     const int g = r / MG, j = r - g * MG;
@@ -662,11 +664,11 @@ __global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restric
     const bool odd = (x0 >> 2) & 1;
     const int oa = odd ? 1 + h : h, ob = odd ? 3 - 3 * h : 2 + h;
     int xa = (x0 - off0) + 4 * oa;
-    if (xa >= M) xa -= M;
+    if (xa >= Mx) xa -= Mx;
     int xb = (x0 - off0) + 4 * ob;
-    if (xb >= M) xb -= M;
+    if (xb >= Mx) xb -= Mx;
     int yy = rv.s[1] + j;
-    if (yy >= M) yy -= M;
+    if (yy >= My) yy -= My;
     const float dyv = ((float)j - rv.f[1]) * dx;
     const float gy = fexp2(-dyv * dyv * a.e2);
     float gw[8], gwd[8], gwd2[8];
@@ -680,20 +682,20 @@ __global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restric
         gwd2[e] = gwd[e] * dxe;
     }
     auto colof = [&](int x) {
-        return (a.tiled ? (unsigned)((yy >> 2) * (M << 2) + ((x >> 3) << 5) + ((yy & 3) << 3) + (x & 7))
-                        : (unsigned)yy * (unsigned)M + (unsigned)x) *
+        return (a.tiled ? (unsigned)((yy >> 2) * (Mx << 2) + ((x >> 3) << 5) + ((yy & 3) << 3) + (x & 7))
+                        : (unsigned)yy * (unsigned)Mx + (unsigned)x) *
                4u;
     };
     const unsigned cola = colof(xa), colb = colof(xb);
     // quads of four x points that meet the support [0, M_G)
     const bool needa = live && 4 * oa - off0 < MG;
     const bool needb = live && 4 * ob - off0 < MG;
-    const size_t M3 = (size_t)M * M * M;
+    const size_t M3 = (size_t)Mx * My * Mz;
     const int bytes = (int)(M3 * sizeof(float));
     const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(grid), (short)0, bytes, kBufferWord3);
     const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(grid + M3), (short)0, bytes, kBufferWord3);
     const __amdgpu_buffer_rsrc_t rs2 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(grid + 2 * M3), (short)0, bytes, kBufferWord3);
-    const unsigned plane = (unsigned)M * (unsigned)M * 4u;
+    const unsigned plane = (unsigned)Mx * (unsigned)My * 4u;
     int z = rv.s[2];
     unsigned zoff = (unsigned)z * plane;
     __syncthreads();
@@ -713,7 +715,7 @@ __global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restric
             u[1][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs1, (int)(zoff + colb), 0, 0));
             u[2][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs2, (int)(zoff + colb), 0, 0));
         }
-        if (++z == M) {
+        if (++z == Mz) {
             z = 0;
             zoff = 0;
         } else {
@@ -775,6 +777,8 @@ template <typename R>
 GridArgs<R> make_args(const fcm_plan_impl* P) {
     GridArgs<R> a;
     a.M = P->M;
+    a.My = P->My;
+    a.Mz = P->Mz;
     a.MG = P->MG;
     a.N = (int)P->N;
     a.TX = P->TX;
@@ -848,7 +852,8 @@ hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W,
     dim3 g((unsigned)((P->N + 3) / 4)), b(256);
     const GridRec<R>* rec = (const GridRec<R>*)P->grec;
     if constexpr (sizeof(R) == sizeof(float)) {
-        if (P->M % 4 == 0 && P->MG <= 13 && a.same_width && P->M <= 512) {
+        if (P->M % 4 == 0 && P->MG <= 13 && a.same_width &&
+            (size_t)P->M * P->My * P->Mz <= (size_t)512 * 512 * 512) {
             const int ppw = std::min(4, 32 / P->MG);
             dim3 g8((unsigned)((P->N + 4 * ppw - 1) / (4 * ppw)));
             if (W == nullptr)

@@ -88,7 +88,8 @@ __device__ inline int fast_div(int j, int d, unsigned m) {
 // Scalars of the grid kernels (one plan).
 template <typename R>
 struct GridArgs {
-    int M, MG, N;
+    int M, My, Mz;                 // grid points along x, y, z
+    int MG, N;
     int TX, TY, TZ;                // spread tile (points)
     int nbx, nby, nbz;             // tiles (= bins) per axis
     int backx, backy, backz;       // bins scanned before the tile's own
@@ -103,8 +104,12 @@ struct GridArgs {
 };
 
 struct PairArgs {
-    int N, m;                      // particles, cells per axis
-    double L, cw, rc2;
+    int N;
+    int mx, my, mz;                // pair cells per axis
+    double Lx, Ly, Lz;             // box sides
+    double iLx, iLy, iLz;          // and their reciprocals
+    double cwx, cwy, cwz;          // cell widths
+    double rc2;
     double eta, sigma, sigmaD, Sigma, SigmaD;
     double selfVF, selfOT;
     int with_pairs;                // 0 = only self corrections (R_c = 0)
@@ -121,24 +126,28 @@ struct fcm_plan_impl {
     int64_t N;
     int64_t Ncap;          // particles the buffers hold
     int cells_cap;         // pair cells the buffers hold
-    double L, a, eta;
+    double L, a, eta;      // L: box side along x
+    double Ly, Lz;         // box sides along y and z (L for a cube)
     double sigma, sigmaD, Sigma, SigmaD;
-    double rc, dx;
-    int M, H, MG;
+    double rc, dx;         // dx: grid spacing, the same on all axes
+    int M, H, MG;          // M: grid points along x, H = M / 2
+    int My, Mz;            // grid points along y and z (M for a cube)
+    int cubic;             // M == My == Mz
     int precision, kahan;
     // spread tiling / grid bins
     int TX, TY, TZ, nbx, nby, nbz, nbins;
     int backx, backy, backz;
-    // pair cells
-    int m, ncells;
-    // FFT
-    fcm::RadixPlan radM, radH;
+    // pair cells: m along x, mcy and mcz along y and z
+    int m, mcy, mcz, ncells;
+    // FFT: radH (length M/2, the x pass), radY and radZ (lengths My and Mz);
+    // twiddle tables of lengths M, My, Mz one after the other in twid
+    fcm::RadixPlan radH, radY, radZ;
     int Wx, Wy, Wz;
     // closed-form constants
     double selfVF, selfOT;
     // device buffers
     void* grid;            // 3 M^3 reals (working field / spectrum)
-    void* twid;            // M complex: exp(-2 pi i m / M), in the grid precision
+    void* twid;            // M + My + Mz complex: exp(-2 pi i m / n) for n = M, My, Mz
     int* counts;           // nbins + ncells (+2) counters
     int* starts;           // exclusive scans: bins then cells
     int* keys;             // 2N keys (bin, cell)
@@ -210,11 +219,11 @@ hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool torque
 
 // plan construction pieces (fcm_api.hip), shared with the request server
 int fft_maxe(int precision, bool zpass);
-int plan_derive(fcm_plan_impl* P, int64_t N, double L, double a, double sigma_delta, int grid,
-                double r_cut, const fcm_options* opt);
+int plan_derive(fcm_plan_impl* P, int64_t N, const double L[3], double a, double sigma_delta,
+                const int grid[3], double r_cut, const fcm_options* opt);
 int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap);
 int plan_rebind(fcm_plan_impl* P, const fcm_plan_impl* derived);
 void plan_free(fcm_plan_impl* P);
-int64_t plan_bytes(int64_t ncap, int grid, int precision, int cellcap, int nbins);
+int64_t plan_bytes(int64_t ncap, const int grid[3], int precision, int cellcap, int nbins);
 
 }  // namespace fcm

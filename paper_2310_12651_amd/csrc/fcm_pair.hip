@@ -133,11 +133,12 @@ __device__ inline void add_pair(double x0, double x1, double x2, double r2, cons
     w[2] += c.fof * (F0 * x1 - F1 * x0) + c.Aot * T2 + c.Bot * h2 * hT;
 }
 
-__device__ inline double4 min_image(double4 p, double4 o, double L, double iL) {
+// minimum image of p - o in the box of sides a.Lx, a.Ly, a.Lz
+__device__ inline double4 min_image(double4 p, double4 o, const PairArgs& a) {
     double x0 = p.x - o.x, x1 = p.y - o.y, x2 = p.z - o.z;
-    x0 -= L * rint(x0 * iL);
-    x1 -= L * rint(x1 * iL);
-    x2 -= L * rint(x2 * iL);
+    x0 -= a.Lx * rint(x0 * a.iLx);
+    x1 -= a.Ly * rint(x1 * a.iLy);
+    x2 -= a.Lz * rint(x2 * a.iLz);
     return make_double4(x0, x1, x2, x0 * x0 + x1 * x1 + x2 * x2);
 }
 
@@ -148,26 +149,25 @@ template <class Hit>
 __device__ inline void scan_layer(const double4* __restrict__ pos4, const int* __restrict__ cell_start,
                                   const PairArgs& a, int j, double4 mp, int cell, int layer,
                                   Hit&& hit) {
-    const double L = a.L, iL = 1.0 / a.L;
-    const int m = a.m;
-    const int cx = cell % m, cy = (cell / m) % m, cz = cell / (m * m);
+    const int mx = a.mx, my = a.my, mz = a.mz;
+    const int cx = cell % mx, cy = (cell / mx) % my, cz = cell / (mx * my);
     int nz = cz + layer - 1;
-    nz = nz < 0 ? nz + m : (nz >= m ? nz - m : nz);
+    nz = nz < 0 ? nz + mz : (nz >= mz ? nz - mz : nz);
     // x neighbours cx-1, cx, cx+1 (mod m) of the three rows: one or two runs of cells
     int rb[6], re[6];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         int ny = cy + r - 1;
-        ny = ny < 0 ? ny + m : (ny >= m ? ny - m : ny);
-        const int row = m * (ny + m * nz);
+        ny = ny < 0 ? ny + my : (ny >= my ? ny - my : ny);
+        const int row = mx * (ny + my * nz);
         if (cx == 0) {
-            rb[2 * r] = cell_start[row + m - 1];
-            re[2 * r] = cell_start[row + m];
+            rb[2 * r] = cell_start[row + mx - 1];
+            re[2 * r] = cell_start[row + mx];
             rb[2 * r + 1] = cell_start[row];
             re[2 * r + 1] = cell_start[row + 2];
-        } else if (cx == m - 1) {
-            rb[2 * r] = cell_start[row + m - 2];
-            re[2 * r] = cell_start[row + m];
+        } else if (cx == mx - 1) {
+            rb[2 * r] = cell_start[row + mx - 2];
+            re[2 * r] = cell_start[row + mx];
             rb[2 * r + 1] = cell_start[row];
             re[2 * r + 1] = cell_start[row + 1];
         } else {
@@ -188,7 +188,7 @@ __device__ inline void scan_layer(const double4* __restrict__ pos4, const int* _
             for (int u = 0; u < 4; ++u) {
                 const int q = q0 + u;
                 if (q < e) {
-                    const double4 x = min_image(mp, c[u], L, iL);
+                    const double4 x = min_image(mp, c[u], a);
                     if (q != j && x.w < a.rc2) hit(q);
                 }
             }
@@ -231,7 +231,6 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restr
     const int pl = tid / 3, layer = tid - 3 * pl;  // local particle, z layer
     const int j = base + pl;
     const bool active = tid < kPairThreads && j < a.N;
-    const double L = a.L, iL = 1.0 / a.L;
     const size_t t0 = (size_t)3 * base;          // scan thread of local thread 0
     const int ntrue = (active && a.with_pairs) ? count[t0 + tid] : 0;
     const int nh = min(ntrue, kPairCap);
@@ -269,7 +268,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restr
                 else hi = mid - 1;
             }
             const int q = hits[(t0 + lo) * kPairCap + (e - qoff[lo])];
-            const double4 y = min_image(pos4[base + lo / 3], pos4[q], L, iL);
+            const double4 y = min_image(pos4[base + lo / 3], pos4[q], a);
             double rv[3] = {0, 0, 0}, rw[3] = {0, 0, 0};
             add_pair<SAME>(y.x, y.y, y.z, y.w, rec[q], a, rv, rw);
             res[tid][0] = rv[0];
@@ -302,7 +301,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restr
         int k = 0;
         scan_layer(pos4, cell_start, a, j, mp, rec[j].cell, layer, [&](int q) {
             if (k++ >= kPairCap) {
-                const double4 y = min_image(mp, pos4[q], L, iL);
+                const double4 y = min_image(mp, pos4[q], a);
                 add_pair<SAME>(y.x, y.y, y.z, y.w, rec[q], a, pv, pw);
             }
         });
@@ -355,9 +354,18 @@ hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torq
                        hipStream_t st, bool store, bool scan) {
     PairArgs a;
     a.N = (int)P->N;
-    a.m = P->m;
-    a.L = P->L;
-    a.cw = P->L / P->m;
+    a.mx = P->m;
+    a.my = P->mcy;
+    a.mz = P->mcz;
+    a.Lx = P->L;
+    a.Ly = P->Ly;
+    a.Lz = P->Lz;
+    a.iLx = 1.0 / P->L;
+    a.iLy = 1.0 / P->Ly;
+    a.iLz = 1.0 / P->Lz;
+    a.cwx = P->L / P->m;
+    a.cwy = P->Ly / P->mcy;
+    a.cwz = P->Lz / P->mcz;
     a.rc2 = P->rc * P->rc;
     a.eta = P->eta;
     a.sigma = P->sigma;

@@ -97,7 +97,9 @@ int derive_request(const fcm_server_options& o, const fcm_request& r, fcm_plan_i
     opt.precision = o.precision;
     opt.kahan = o.kahan;
     memset(d, 0, sizeof(*d));
-    return fcm::plan_derive(d, r.N, r.L, r.a, r.sigma_delta, r.grid, r.r_cut, &opt);
+    const double L3[3] = {r.L, r.L, r.L};
+    const int g3[3] = {r.grid, r.grid, r.grid};
+    return fcm::plan_derive(d, r.N, L3, r.a, r.sigma_delta, g3, r.r_cut, &opt);
 }
 
 }  // namespace
@@ -140,7 +142,8 @@ CachedPlan* fcm_server_impl::plan_for_locked(const fcm_plan_impl& d, int* status
     const int cellcap = (int)std::min<int64_t>(round_up_pow2(d.ncells), (int64_t)fcm::kMaxCellsPerAxis *
                                                                             fcm::kMaxCellsPerAxis *
                                                                             fcm::kMaxCellsPerAxis);
-    const int64_t bytes = fcm::plan_bytes(ncap, d.M, d.precision, cellcap, d.nbins);
+    const int g3[3] = {d.M, d.My, d.Mz};
+    const int64_t bytes = fcm::plan_bytes(ncap, g3, d.precision, cellcap, d.nbins);
     if (bytes > budget) {
         *status = FCM_ENOMEM;
         return nullptr;

@@ -22,11 +22,12 @@ constexpr int kScanTile = kScanThreads * kScanPerThread;   // 4096
 constexpr int kMaxScanTiles = 2048;              // scan_tmp entries
 
 struct HashArgs {
-    int N, M, MG;
+    int N, MG;
+    int Mv[3];                     // grid points per axis
     int TX, TY, TZ, nbx, nby, nbz, nbins;
-    int m;
+    int mc[3];                     // pair cells per axis
     int ident;                     // pair order = caller's order (no cell search)
-    double L, dx, cw;
+    double Lv[3], dx, cw[3];       // box sides, grid spacing, cell widths
 };
 
 constexpr int kShortSegment = 64;      // ordered by one thread
@@ -74,14 +75,14 @@ __global__ void k_hash(const double* __restrict__ pos, HashArgs h, int* __restri
     int s[3], c[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double w = wrap_coord(pos[3 * (int64_t)i + a], h.L, &bad);
-        s[a] = wrap_index(support_start(w, h.dx, h.MG), h.M);
-        int cc = (int)floor(w / h.cw);
-        c[a] = cc < 0 ? 0 : (cc >= h.m ? h.m - 1 : cc);
+        double w = wrap_coord(pos[3 * (int64_t)i + a], h.Lv[a], &bad);
+        s[a] = wrap_index(support_start(w, h.dx, h.MG), h.Mv[a]);
+        int cc = (int)floor(w / h.cw[a]);
+        c[a] = cc < 0 ? 0 : (cc >= h.mc[a] ? h.mc[a] - 1 : cc);
     }
     if (bad) atomicOr(flag, 1);
     int bin = s[0] / h.TX + h.nbx * (s[1] / h.TY + h.nby * (s[2] / h.TZ));
-    int cell = c[0] + h.m * (c[1] + h.m * c[2]);
+    int cell = c[0] + h.mc[0] * (c[1] + h.mc[1] * c[2]);
     keys[i] = bin;
     keys[h.N + i] = cell;
     ranks[i] = atomicAdd(&counts[bin], 1);
@@ -320,16 +321,18 @@ __global__ __launch_bounds__(256) void k_segment_order(const int* __restrict__ s
 template <typename R>
 __global__ void k_place(const double* __restrict__ pos, const double* __restrict__ F,
                         const double* __restrict__ T, const int* __restrict__ inv,
-                        const int* __restrict__ cellkey, int N, int M, int MG, double L, double dx,
-                        double normF, double normT, GridRec<R>* __restrict__ grec,
+                        const int* __restrict__ cellkey, int N, int3 Mv, int MG, double3 Lv,
+                        double dx, double normF, double normT, GridRec<R>* __restrict__ grec,
                         PairRec* __restrict__ prec, double4* __restrict__ pos4) {
+    const int Ma[3] = {Mv.x, Mv.y, Mv.z};
+    const double La[3] = {Lv.x, Lv.y, Lv.z};
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     int bad = 0;
     double w[3], f[3], t[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        w[a] = wrap_coord(pos[3 * (int64_t)i + a], L, &bad);
+        w[a] = wrap_coord(pos[3 * (int64_t)i + a], La[a], &bad);
         f[a] = F ? F[3 * (int64_t)i + a] : 0.0;
         t[a] = T ? T[3 * (int64_t)i + a] : 0.0;
     }
@@ -338,7 +341,7 @@ __global__ void k_place(const double* __restrict__ pos, const double* __restrict
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int su = support_start(w[a], dx, MG);
-            r.s[a] = wrap_index(su, M);
+            r.s[a] = wrap_index(su, Ma[a]);
             r.f[a] = (R)(w[a] / dx - (double)su);
             r.F[a] = (R)(f[a] * normF);
             r.T[a] = (R)(t[a] * normT);
@@ -375,7 +378,9 @@ hipError_t launch_fill(int* p, int n, int v, hipStream_t st) {
 hipError_t launch_hash(const fcm_plan_impl* P, const double* pos, hipStream_t st) {
     HashArgs h;
     h.N = (int)P->N;
-    h.M = P->M;
+    h.Mv[0] = P->M;
+    h.Mv[1] = P->My;
+    h.Mv[2] = P->Mz;
     h.MG = P->MG;
     h.TX = P->TX;
     h.TY = P->TY;
@@ -384,11 +389,15 @@ hipError_t launch_hash(const fcm_plan_impl* P, const double* pos, hipStream_t st
     h.nby = P->nby;
     h.nbz = P->nbz;
     h.nbins = P->nbins;
-    h.m = P->m;
+    h.mc[0] = P->m;
+    h.mc[1] = P->mcy;
+    h.mc[2] = P->mcz;
     h.ident = P->rc > 0.0 ? 0 : 1;
-    h.L = P->L;
+    h.Lv[0] = P->L;
+    h.Lv[1] = P->Ly;
+    h.Lv[2] = P->Lz;
     h.dx = P->dx;
-    h.cw = P->L / P->m;
+    for (int d = 0; d < 3; ++d) h.cw[d] = h.Lv[d] / h.mc[d];
     hipLaunchKernelGGL(k_hash, dim3(blocks_for(h.N, 256)), dim3(256), 0, st, pos, h, P->keys,
                        P->ranks, P->counts, P->flag);
     return hipGetLastError();
@@ -434,13 +443,15 @@ hipError_t place(const fcm_plan_impl* P, const double* pos, const double* F, con
         pow(2.0 * pi * P->SigmaD * P->SigmaD, -1.5) / (2.0 * P->SigmaD * P->SigmaD);
     const dim3 g(blocks_for(N, 256)), b(256);
     PairRec* pr = pair ? P->prec : nullptr;
+    const int3 Mv = make_int3(P->M, P->My, P->Mz);
+    const double3 Lv = make_double3(P->L, P->Ly, P->Lz);
     if (P->precision == FCM_FP64)
-        hipLaunchKernelGGL(k_place<double>, g, b, 0, st, pos, F, T, P->ranks, P->keys + N, N, P->M,
-                           P->MG, P->L, P->dx, normF, normT,
+        hipLaunchKernelGGL(k_place<double>, g, b, 0, st, pos, F, T, P->ranks, P->keys + N, N, Mv,
+                           P->MG, Lv, P->dx, normF, normT,
                            grid ? (GridRec<double>*)P->grec : nullptr, pr, P->ppos);
     else
-        hipLaunchKernelGGL(k_place<float>, g, b, 0, st, pos, F, T, P->ranks, P->keys + N, N, P->M,
-                           P->MG, P->L, P->dx, normF, normT,
+        hipLaunchKernelGGL(k_place<float>, g, b, 0, st, pos, F, T, P->ranks, P->keys + N, N, Mv,
+                           P->MG, Lv, P->dx, normF, normT,
                            grid ? (GridRec<float>*)P->grec : nullptr, pr, P->ppos);
     return hipGetLastError();
 }
