@@ -138,6 +138,31 @@ int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double*
 int fcm_mobility_repeat(fcm_plan_t p, const double* F, const double* T, double* V,
                         double* Omega, void* stream);
 
+/*
+ * Brownian velocities (force-free particles): V = sqrt(2 kT) [M~^(1/2) xi_g +
+ * (M - M~)^(1/2) xi_p], whose covariance is 2 kT M (the VF block), built on the
+ * positive splitting of Sec. 3.3 as the paper proposes in Sec. 7: the grid part
+ * by fluctuating FCM, sqrt(2 kT / dV) J~[G^(1/2) xi_g] with G^(1/2) the Fourier
+ * multiplier P(k) / sqrt(eta k^2) (k = 0 and the Nyquist planes removed), the
+ * pair part by Lanczos steps whose matrix products are the pair-correction pass.
+ *   pos     : device N x 3 FP64 positions.
+ *   xi_grid : device noise field, 3 x grid[2] x grid[1] x grid[0] values (x
+ *             fastest) in the plan's grid precision, i.i.d. N(0, 1); not modified.
+ *   xi_pair : device N x 3 FP64 i.i.d. N(0, 1) (unused, may be NULL, when the
+ *             plan needs no correction: standard FCM).
+ *   kT      : thermal energy (>= 0).
+ *   tol     : Lanczos stops when the relative change of the pair part is below tol.
+ *   V       : device N x 3 FP64, overwritten.  iterations: host, Lanczos steps taken.
+ * The caller supplies every random number, so results are reproducible.  The
+ * Lanczos recurrence synchronises the stream at each step.  Requires
+ * fcm_brownian_reserve first when a correction is needed (FCM_EINVAL otherwise).
+ */
+int fcm_brownian(fcm_plan_t p, const double* pos, const void* xi_grid, const double* xi_pair,
+                 double kT, double tol, double* V, int* iterations, void* stream);
+/* Allocates the Lanczos basis of fcm_brownian for up to max_iter steps (1..64):
+ * (max_iter + 1) x 3N FP64.  The one call besides plan creation that allocates. */
+int fcm_brownian_reserve(fcm_plan_t p, int max_iter);
+
 /* Stage calls: the operators of Sec. 2.1 / 3.1 / 3.4 one at a time. */
 
 /* grid_out = J~^dagger[F] + N~^dagger[T] on the grid (modified force kernel of

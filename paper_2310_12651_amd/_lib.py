@@ -18,7 +18,7 @@ FCM_FP64, FCM_FP32_BULK = 0, 1
 EXPORTS = [
     "fcm_options_default", "fcm_plan", "fcm_plan_ex", "fcm_plan_box", "fcm_plan_box_info",
     "fcm_plan_destroy", "fcm_mobility",
-    "fcm_mobility_repeat", "fcm_spread", "fcm_solve", "fcm_interp", "fcm_correct", "fcm_plan_info",
+    "fcm_mobility_repeat", "fcm_brownian", "fcm_brownian_reserve", "fcm_spread", "fcm_solve", "fcm_interp", "fcm_correct", "fcm_plan_info",
     "fcm_plan_footprint", "fcm_plan_last_error", "fcm_status_string", "fcm_plan_set_timing",
     "fcm_plan_stage_times",
 ]
@@ -64,6 +64,8 @@ def library():
         "fcm_plan_destroy": ([vp], ci),
         "fcm_mobility": ([vp, dp, dp, dp, dp, dp, vp], ci),
         "fcm_mobility_repeat": ([vp, dp, dp, dp, dp, vp], ci),
+        "fcm_brownian": ([vp, dp, vp, dp, cd, cd, dp, ctypes.POINTER(ci), vp], ci),
+        "fcm_brownian_reserve": ([vp, ci], ci),
         "fcm_spread": ([vp, dp, dp, dp, vp, vp], ci),
         "fcm_solve": ([vp, vp, vp], ci),
         "fcm_interp": ([vp, dp, vp, dp, dp, vp], ci),
@@ -220,6 +222,22 @@ class Plan:
                                              _ptr(Omega, "Omega", N, f64, True), _stream(stream)),
                "fcm_mobility_repeat")
         return V, Omega
+
+    def brownian(self, pos, xi_grid, xi_pair, kT, tol=1e-8, V=None, max_iter=48, stream=None):
+        """fcm_brownian: Brownian velocities from the given noise; returns (V, Lanczos steps)."""
+        import torch
+        N = self.N
+        if V is None:
+            V = torch.empty((N, 3), dtype=torch.float64, device=pos.device)
+        self._check_grid(xi_grid)
+        _check(library().fcm_brownian_reserve(self.handle, int(max_iter)), "fcm_brownian_reserve")
+        it = ctypes.c_int()
+        f64 = torch.float64
+        _check(library().fcm_brownian(self.handle, _ptr(pos, "pos", N, f64), ctypes.c_void_p(xi_grid.data_ptr()),
+                                      _ptr(xi_pair, "xi_pair", N, f64, True), float(kT), float(tol),
+                                      _ptr(V, "V", N, f64), ctypes.byref(it), _stream(stream)),
+               "fcm_brownian")
+        return V, it.value
 
     def spread(self, pos, F, T=None, grid_out=None, stream=None):
         import torch

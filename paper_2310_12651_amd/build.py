@@ -14,7 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfcm.so")
-SOURCES = ["fcm_api.hip", "fcm_sort.hip", "fcm_grid.hip", "fcm_fft.hip", "fcm_pair.hip", "fcm_server.hip"]
+SOURCES = ["fcm_api.hip", "fcm_sort.hip", "fcm_grid.hip", "fcm_fft.hip", "fcm_pair.hip", "fcm_server.hip",
+           "fcm_brownian.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -154,7 +154,7 @@ void free_plan(fcm_plan_impl* P) {
     free_events(P);
     void* bufs[] = {P->grid,  P->twid, P->counts, P->starts,    P->keys,       P->ranks,
                     P->perm,  P->scan_tmp, P->grec, P->prec,    P->ppos,       P->flag,
-                    P->pair_hits, P->pair_count, P->corr};
+                    P->pair_hits, P->pair_count, P->corr, P->krylov, P->partial};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (P->fork) (void)hipEventDestroy(P->fork);
@@ -334,6 +334,7 @@ int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
     FCM_ALLOC(P->pair_hits, (size_t)3 * ncap * kPairCap * sizeof(int));
     FCM_ALLOC(P->pair_count, (size_t)3 * ncap * sizeof(int));
     FCM_ALLOC(P->corr, (size_t)6 * ncap * sizeof(double));
+    FCM_ALLOC(P->partial, 1024 * sizeof(double));
     FCM_ALLOC(P->flag, 16 * sizeof(int));
 #undef FCM_ALLOC
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking);
@@ -592,6 +593,59 @@ int fcm_mobility_repeat(fcm_plan_t p, const double* F, const double* T, double* 
     mark(8);
     mark(9);
     if (e != hipSuccess) p->repeat_ok = 0;
+    return map_err(e);
+}
+
+int fcm_brownian_reserve(fcm_plan_t p, int max_iter) {
+    if (!p || max_iter < 1 || max_iter > 64) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    if (p->krylov && p->krylov_cap >= max_iter) return FCM_OK;
+    if (p->krylov) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(p->krylov);
+        p->krylov = nullptr;
+        p->krylov_cap = 0;
+    }
+    hipError_t e = hipMalloc((void**)&p->krylov, (size_t)(max_iter + 1) * 3 * p->Ncap * sizeof(double));
+    if (e != hipSuccess) {
+        p->krylov = nullptr;
+        return map_err(e);
+    }
+    p->krylov_cap = max_iter;
+    return FCM_OK;
+}
+
+int fcm_brownian(fcm_plan_t p, const double* pos, const void* xi_grid, const double* xi_pair,
+                 double kT, double tol, double* V, int* iterations, void* stream) {
+    if (!p || !pos || !xi_grid || !V || !(kT >= 0.0) || !isfinite(kT) || !(tol > 0.0))
+        return FCM_EINVAL;
+    const bool corr = needs_correction(p);
+    if (corr && (!xi_pair || !p->krylov)) return FCM_EINVAL;
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    const int n = (int)(3 * p->N);
+    hipError_t e = sort_particles(p, pos, st);
+    if (e == hipSuccess)
+        e = corr ? launch_gather_both(p, pos, nullptr, nullptr, st)
+                 : launch_gather_grid(p, pos, nullptr, nullptr, st);
+    int it = 0;
+    // pair part y = C^(1/2) xi_pair into the correction buffer
+    if (e == hipSuccess && corr) e = lanczos_sqrt_pair(p, xi_pair, p->corr, tol, &it, st);
+    // grid part: J~ G^(1/2) xi_grid, with the noise copied into the plan's grid
+    const size_t nb = (size_t)3 * p->M * p->My * p->Mz * real_size(p->precision);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->grid, xi_grid, nb, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = launch_solve(p, p->grid, st, nullptr, false, true);
+    if (e == hipSuccess) e = launch_interp(p, p->grid, V, nullptr, st, false, nullptr);
+    // V = sqrt(2 kT / dV) J~ G^(1/2) xi_grid + sqrt(2 kT) y
+    const double dV = p->dx * p->dx * p->dx;
+    if (e == hipSuccess) {
+        if (corr)
+            e = launch_axpby(sqrt(2.0 * kT), p->corr, sqrt(2.0 * kT / dV), V, n, st);
+        else
+            e = launch_axpby(0.0, V, sqrt(2.0 * kT / dV), V, n, st);
+    }
+    if (iterations) *iterations = it;
     return map_err(e);
 }
 

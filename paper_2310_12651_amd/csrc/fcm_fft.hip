@@ -290,7 +290,8 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_y(C2<R>* __restrict__ spec,
 
 struct ProjArgs {
     double kux, kuy, kuz;   // 2 pi / L along x, y, z
-    double scale;           // 1 / (eta Mx My Mz)
+    double scale;           // 1 / (eta Mx My Mz); square root: 1 / (sqrt(eta) Mx My Mz)
+    int root;               // multiply by P(k) / sqrt(eta k^2) instead of P(k) / (eta k^2)
 };
 
 // z pass: forward FFT along z, projection / (eta k^2), inverse FFT along z
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_solve(C2<R>* __restrict__
             const R ik2 = (R)1 / k2;
             const C2<R> kf = {(kx * f0.x + ky * f1.x + kz * f2.x) * ik2,
                               (kx * f0.y + ky * f1.y + kz * f2.y) * ik2};
-            const R s = sc * ik2;
+            const R s = pa.root ? sc * sqrt(ik2) : sc * ik2;
             u0 = C2<R>{(f0.x - kx * kf.x) * s, (f0.y - kx * kf.y) * s};
             u1 = C2<R>{(f1.x - ky * kf.x) * s, (f1.y - ky * kf.y) * s};
             u2 = C2<R>{(f2.x - kz * kf.x) * s, (f2.y - kz * kf.y) * s};
@@ -590,7 +591,7 @@ __global__ __launch_bounds__(W * N2) void k_fft_z_solve_reg(C2<float>* __restric
         const C2<float> f0 = v[0][i], f1 = v[1][i], f2 = v[2][i];
         const C2<float> kf = {(kx * f0.x + ky * f1.x + kz * f2.x) * ik2,
                               (kx * f0.y + ky * f1.y + kz * f2.y) * ik2};
-        const float s = sc * ik2;
+        const float s = pa.root ? sc * sqrtf(ik2) : sc * ik2;
         v[0][i] = C2<float>{(f0.x - kx * kf.x) * s, (f0.y - kx * kf.y) * s};
         v[1][i] = C2<float>{(f1.x - ky * kf.x) * s, (f1.y - ky * kf.y) * s};
         v[2][i] = C2<float>{(f2.x - kz * kf.x) * s, (f2.y - kz * kf.y) * s};
@@ -763,19 +764,22 @@ void z_lds(const fcm_plan_impl* P, C2<R>* spec, const C2<R>* twz, hipStream_t st
                        twz, Mz, H, P->My, P->radZ, P->Wz, __builtin_ctz(P->Wz), pa);
 }
 
-ProjArgs proj_args(const fcm_plan_impl* P) {
+// root: the square root of the solve's multiplier (Brownian grid part)
+ProjArgs proj_args(const fcm_plan_impl* P, bool root) {
     const double twopi = 2.0 * 3.14159265358979323846;
     ProjArgs pa;
     pa.kux = twopi / P->L;
     pa.kuy = twopi / P->Ly;
     pa.kuz = twopi / P->Lz;
-    pa.scale = 1.0 / (P->eta * (double)P->M * P->My * P->Mz);
+    pa.scale = 1.0 / ((root ? sqrt(P->eta) : P->eta) * (double)P->M * P->My * P->Mz);
+    pa.root = root ? 1 : 0;
     return pa;
 }
 
 // FP32 solve with register passes (RegPlan sizes)
 template <int XN1, int XN2, int YN1, int YN2, int YW, bool ZREG>
-hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEvent_t* ev, bool tiled) {
+hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEvent_t* ev, bool tiled,
+                     bool root) {
     using X = XGeom<XN1, XN2>;
     using Y = ColGeom<YN1, YN2, YW>;
     static_assert(2 * X::H == Y::M, "x and y factorisations of the same M");
@@ -799,9 +803,9 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     mark(2);
     if constexpr (ZREG)
         hipLaunchKernelGGL((k_fft_z_solve_reg<YN1, YN2, YW>), dim3(Y::NG * M), dim3(Y::NT), 0, st, spec,
-                           tw, proj_args(P));
+                           tw, proj_args(P, root));
     else
-        z_lds<float, 8>(P, spec, tw, st, proj_args(P));
+        z_lds<float, 8>(P, spec, tw, st, proj_args(P, root));
     mark(3);
     hipLaunchKernelGGL((k_fft_y_reg<YN1, YN2, YW, 1>), dim3(Y::NG * 3 * M), dim3(Y::NT), 0, st, spec,
                        tw);
@@ -844,11 +848,12 @@ bool reg_size(int M) {
 }
 
 template <typename R, int MX, int MZ>
-hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* ev, bool tiled) {
+hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* ev, bool tiled,
+                   bool root) {
     if constexpr (sizeof(R) == sizeof(float)) {
 #define FCM_REG_CASE(m, a, b, c, d, e, f) \
     case m:                               \
-        return solve_reg<a, b, c, d, e, f>(P, grid, st, ev, tiled);
+        return solve_reg<a, b, c, d, e, f>(P, grid, st, ev, tiled, root);
         if (P->cubic) switch (P->M) {
                 FCM_REG_SIZES(FCM_REG_CASE)
                 default: break;
@@ -879,7 +884,7 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
     hipLaunchKernelGGL((k_fft_y<R, -1, MX>), dim3(ngy * 3 * Mz), dim3(kFFTThreads), shy, st, spec, twy,
                        My, H, P->radY, P->Wy, lwy);
     mark(2);
-    z_lds<R, MZ>(P, spec, twz, st, proj_args(P));
+    z_lds<R, MZ>(P, spec, twz, st, proj_args(P, root));
     mark(3);
     hipLaunchKernelGGL((k_fft_y<R, 1, MX>), dim3(ngy * 3 * Mz), dim3(kFFTThreads), shy, st, spec, twy,
                        My, H, P->radY, P->Wy, lwy);
@@ -906,9 +911,9 @@ bool solve_tiles(const fcm_plan_impl* P) {
 }
 
 hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st, hipEvent_t* ev,
-                        bool tiled) {
-    if (P->precision == FCM_FP64) return solve_r<double, 8, 4>(P, (double*)grid, st, ev, false);
-    return solve_r<float, 16, 8>(P, (float*)grid, st, ev, tiled && solve_tiles(P));
+                        bool tiled, bool root) {
+    if (P->precision == FCM_FP64) return solve_r<double, 8, 4>(P, (double*)grid, st, ev, false, root);
+    return solve_r<float, 16, 8>(P, (float*)grid, st, ev, tiled && solve_tiles(P), root);
 }
 
 }  // namespace fcm

@@ -160,6 +160,9 @@ struct fcm_plan_impl {
     int* pair_hits;        // 3N x kPairCap neighbours found by the pair scan
     int* pair_count;       // 3N neighbour counts
     double* corr;          // 6N: pair + self corrections of V (3N) then Omega (3N)
+    double* krylov;        // Brownian pair part: (krylov_cap + 1) x 3N Lanczos basis, or NULL
+    int krylov_cap;        // Lanczos steps the basis holds
+    double* partial;       // 1024 partial sums of the vector reductions
     hipStream_t side;      // the pair correction runs here, beside spread and FFT
     hipEvent_t fork, join; // sorted records ready / corrections ready
     int* flag;             // [0] = non-finite position seen
@@ -209,13 +212,25 @@ hipError_t launch_interp(const fcm_plan_impl* P, const void* grid, double* V, do
 // tiled: the force field arrives, and the velocity field leaves, in the x-y
 // tiled layout (tiles of 8 x by 4 y, x fastest inside a tile, tiles x fastest,
 // then tile rows, then z); only when the plan supports it (solve_tiles)
+// root: multiply by the square root P(k) / sqrt(eta k^2) of the solve's
+// Fourier multiplier instead (the grid part of Brownian velocities)
 hipError_t launch_solve(const fcm_plan_impl* P, void* grid, hipStream_t st,
-                        hipEvent_t* ev = nullptr, bool tiled = false);
+                        hipEvent_t* ev = nullptr, bool tiled = false, bool root = false);
 bool solve_tiles(const fcm_plan_impl* P);
 // store: write the corrections to V and W (else add them); scan: search the
 // neighbours first (else reuse the lists of the last search, same positions)
 hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool torque,
                        hipStream_t st, bool store = false, bool scan = true);
+
+// Brownian pair part: y = C^(1/2) xi (caller order, N x 3) for the VF
+// correction matrix C, by Lanczos steps (at most the plan's krylov_cap) until
+// the relative change of y is below tol; needs the sorted records of the
+// positions; iters receives the steps taken.  Host-synchronous.
+hipError_t lanczos_sqrt_pair(fcm_plan_impl* P, const double* xi, double* y, double tol,
+                             int* iters, hipStream_t st);
+// y = alpha x + beta y over n doubles
+hipError_t launch_axpby(double alpha, const double* x, double beta, double* y, int n,
+                        hipStream_t st);
 
 // plan construction pieces (fcm_api.hip), shared with the request server
 int fft_maxe(int precision, bool zpass);
