@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--tune-sigma", action="store_true",
                     help="instead of the headline run: evaluations/s against Sigma/sigma at "
                          "a/L = 1/400 for the volume fractions of Table 3 (its optimum on this GPU)")
+    ap.add_argument("--brownian", action="store_true",
+                    help="instead of the headline run: time fcm_brownian on the workload (FP32 bulk "
+                         "and FP64, Lanczos tolerance 1e-6)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="before timing, copy a field-sized device buffer 3 times (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -105,6 +108,27 @@ def traffic_for(stage, workload):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def valu_for(stage, workload):
+    """VALU wave instructions per launch from the committed counter summary of
+    this kernel and workload, or None when absent or taken on another source."""
+    path = os.path.join(ROOT, "profiles", f"valu_{stage}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = SOURCE_OF_STAGE.get(stage, "fcm_fft.hip")
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_2310_12651_amd", "csrc", src), "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != h:
+        return None
+    try:
+        return float(vals["sq_insts_valu_per_dispatch"])
     except (KeyError, ValueError):
         return None
 
@@ -494,6 +518,50 @@ def tune_sigma(args, torch):
                                         "for phi 0.05, 0.2, 0.8, 3.2, 12.8 %; peak ~7e6 PTPS")
 
 
+def brownian_leg(args, torch):
+    """Brownian velocities (fcm_brownian) on the workload: ms per call for FP32
+    bulk and FP64 with seeded noise (grid noise in the grid precision), the
+    Lanczos steps to a relative change of 1e-6, and the deterministic part's
+    ms per call beside it for scale."""
+    import numpy as np
+
+    import workloads
+    from paper_2310_12651_amd import FCM_FP32_BULK, FCM_FP64, Plan
+    w = workloads.workload(WORKLOADS[args.workload])
+    N, M = w["N"], w["grid"]
+    Y = torch.as_tensor(w["Y"], device="cuda")
+    rng = np.random.default_rng(workloads.SEED_BASE + 7)
+    xp = torch.as_tensor(rng.normal(size=(N, 3)), device="cuda")
+    out = {}
+    for name, prec in (("fp32", FCM_FP32_BULK), ("fp64", FCM_FP64)):
+        plan = Plan(N, w["L"], w["a"], w["Sigma"], M, w["R_c"], support=w["M_G"], precision=prec)
+        xg = torch.randn((3, M, M, M), dtype=plan.grid_dtype, device="cuda",
+                         generator=torch.Generator(device="cuda").manual_seed(11))
+        V = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            _, it = plan.brownian(Y, xg, xp, 1.0, tol=1e-6, V=V)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, it = plan.brownian(Y, xg, xp, 1.0, tol=1e-6, V=V)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        F = torch.as_tensor(w["F"], device="cuda")
+        plan.mobility(Y, F, None, V, None, want_omega=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.mobility(Y, F, None, V, None, want_omega=False)
+        torch.cuda.synchronize()
+        ms_det = (time.perf_counter() - t0) * 1e3 / args.steps
+        plan.close()
+        out[name] = dict(ms_per_call=ms, lanczos_steps=it, evals_per_s=N / (ms * 1e-3),
+                         deterministic_force_only_ms=ms_det)
+        log(f"[brownian] {name}: {ms:.3f} ms per call, {it} Lanczos steps; force-only mobility {ms_det:.3f} ms")
+    return dict(metric="Brownian velocities per call (fcm_brownian), wall clock", workload=w["name"],
+                steps=args.steps, **out)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -506,6 +574,9 @@ def main():
     import workloads
     from paper_2310_12651_amd import FCM_FP32_BULK, FCM_FP64, Plan
 
+    if args.brownian:
+        print(json.dumps(brownian_leg(args, torch)), flush=True)
+        return
     if args.tune_sigma:
         print(json.dumps(tune_sigma(args, torch)), flush=True)
         return
@@ -576,6 +647,13 @@ def main():
         roof = dict(kernel=KERNEL_OF_STAGE[dom_grid], bound="hbm", achieved=round(ach, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
                     traffic=tr, algorithmic_bytes=ab, launch_ms=round(stages[dom_grid], 5))
+        # what actually bounds spread and interpolation: VALU issue (a wave64
+        # instruction holds a 16-lane SIMD 4 cycles; 1024 SIMDs at 2.4 GHz),
+        # counted once by rocprofv3 and divided by this run's launch time
+        nv = valu_for(dom_grid, args.workload)
+        if nv is not None:
+            roof["valu_issue"] = dict(wave_instructions=nv, simds=1024, clock_ghz=2.4,
+                                      frac=round(nv * 4 / (1024 * 2.4e9 * stages[dom_grid] * 1e-3), 3))
     per_stage_gbs = {s: round(algorithmic_bytes(w, s) / (stages[s] * 1e-3) / 1e9, 1)
                      for s in grid_stages}
     serving = None
