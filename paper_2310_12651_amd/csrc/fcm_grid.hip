@@ -612,14 +612,17 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
 }
 
 // FP32 interpolation with several particles per wavefront (M divisible by 4,
-// M_G <= 13, Sigma_D = Sigma, one field component addressable with 32-bit byte
+// M_G <= 16, Sigma_D = Sigma, one field component addressable with 32-bit byte
 // offsets).  Lane 32 h + M_G g + j serves particle slot g (g < 32 / M_G, at
-// most four slots), support row j and two aligned quads of four x points (two
-// 16-byte loads; lane h = 0 and h = 1 of a row together cover x0 & ~3 plus 0..15),
-// so at M_G = 10 three particles share a wavefront and 60 of its 64 lanes work.  The per-lane sums follow the factorisation of
-// k_interp4; the two chunks of a row are combined by one lane exchange, the
-// rows of each particle through LDS, in a fixed order.
-template <bool OMEGA>
+// most four slots), support row j and NQ quads of four x points counted from
+// x0 & ~3 (NQ 16-byte loads): quad 2 l + h, l < NQ, taken cyclically from the
+// parity of x0 >> 2, so the two lanes of a row read the two halves of one 8 x 4
+// tile in each load where they can.  NQ = 2 covers 16 points (M_G <= 13), NQ =
+// 3 covers 24 (M_G <= 16, two particles per wavefront); at M_G = 10 three
+// particles share a wavefront and 60 of its 64 lanes work.  The per-lane sums
+// follow the factorisation of k_interp4; the two lanes of a row are combined by
+// one lane exchange, the rows of each particle through LDS, in a fixed order.
+template <bool OMEGA, int NQ>
 __global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restrict__ rec,
                                                  const float* __restrict__ grid, double* __restrict__ V,
                                                  double* __restrict__ W, GridArgs<float> a,
@@ -627,6 +630,7 @@ __global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restric
                                                  const double* __restrict__ corr) {
     constexpr int kSlots = 4;
     constexpr int NV = OMEGA ? 6 : 3;
+    constexpr int NX = 4 * NQ;
     __shared__ ZTab<float> zt[4][kSlots][kMaxSupport];
     __shared__ float red[4][NV][32];
     __shared__ int origs[4][kSlots];
@@ -656,40 +660,35 @@ __global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restric
         zt[wave][g][j] = e;
         if (j == 0) origs[wave][g] = rv.orig;
     }
-    // Row j of the support; the lane's two quads of four x points, counted in
-    // quads from x0 & ~3.  The pairing makes each of the two loads of a
-    // wavefront cover whole 8 x 4 tiles where it can: with the first quad at
-    // an even position both lanes of a row read the same tile in each load.
     const int x0 = rv.s[0], off0 = x0 & 3;
-    const bool odd = (x0 >> 2) & 1;
-    const int oa = odd ? 1 + h : h, ob = odd ? 3 - 3 * h : 2 + h;
-    int xa = (x0 - off0) + 4 * oa;
-    if (xa >= Mx) xa -= Mx;
-    int xb = (x0 - off0) + 4 * ob;
-    if (xb >= Mx) xb -= Mx;
+    const int odd = (x0 >> 2) & 1;
     int yy = rv.s[1] + j;
     if (yy >= My) yy -= My;
     const float dyv = ((float)j - rv.f[1]) * dx;
     const float gy = fexp2(-dyv * dyv * a.e2);
-    float gw[8], gwd[8], gwd2[8];
+    float gw[NX], gwd[NX], gwd2[NX];
+    unsigned col[NQ];
+    bool need[NQ];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int i = 4 * (e < 4 ? oa : ob) + (e & 3) - off0;
-        const float dxe = ((float)i - rv.f[0]) * dx;
-        const float gx = (i >= 0 && i < MG) ? fexp2(-dxe * dxe * a.e2) : 0.0f;
-        gw[e] = gx * gy;
-        gwd[e] = gw[e] * dxe;
-        gwd2[e] = gwd[e] * dxe;
+    for (int l = 0; l < NQ; ++l) {
+        const int o = (2 * l + h + odd) % (2 * NQ);
+        int x = (x0 - off0) + 4 * o;
+        if (x >= Mx) x -= Mx;
+        col[l] = (a.tiled ? (unsigned)((yy >> 2) * (Mx << 2) + ((x >> 3) << 5) + ((yy & 3) << 3) + (x & 7))
+                          : (unsigned)yy * (unsigned)Mx + (unsigned)x) *
+                 4u;
+        // quads of four x points that meet the support [0, M_G)
+        need[l] = live && 4 * o - off0 < MG;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = 4 * o + e - off0;
+            const float dxe = ((float)i - rv.f[0]) * dx;
+            const float gx = (i >= 0 && i < MG) ? fexp2(-dxe * dxe * a.e2) : 0.0f;
+            gw[4 * l + e] = gx * gy;
+            gwd[4 * l + e] = gw[4 * l + e] * dxe;
+            gwd2[4 * l + e] = gwd[4 * l + e] * dxe;
+        }
     }
-    auto colof = [&](int x) {
-        return (a.tiled ? (unsigned)((yy >> 2) * (Mx << 2) + ((x >> 3) << 5) + ((yy & 3) << 3) + (x & 7))
-                        : (unsigned)yy * (unsigned)Mx + (unsigned)x) *
-               4u;
-    };
-    const unsigned cola = colof(xa), colb = colof(xb);
-    // quads of four x points that meet the support [0, M_G)
-    const bool needa = live && 4 * oa - off0 < MG;
-    const bool needb = live && 4 * ob - off0 < MG;
     const size_t M3 = (size_t)Mx * My * Mz;
     const int bytes = (int)(M3 * sizeof(float));
     const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(grid), (short)0, bytes, kBufferWord3);
@@ -702,18 +701,22 @@ __global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restric
     float P[3] = {0, 0, 0}, Rr[3] = {0, 0, 0}, PD2[3] = {0, 0, 0}, PD[2] = {0, 0}, Q[2] = {0, 0};
     for (int k = 0; k < MG; ++k) {
         const ZTab<float> e = zt[wave][gz][k];
-        float4 u[3][2];
+        float u[3][NX];
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) u[cc][0] = u[cc][1] = make_float4(0, 0, 0, 0);
-        if (needa) {
-            u[0][0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs0, (int)(zoff + cola), 0, 0));
-            u[1][0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs1, (int)(zoff + cola), 0, 0));
-            u[2][0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs2, (int)(zoff + cola), 0, 0));
-        }
-        if (needb) {
-            u[0][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs0, (int)(zoff + colb), 0, 0));
-            u[1][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs1, (int)(zoff + colb), 0, 0));
-            u[2][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs2, (int)(zoff + colb), 0, 0));
+        for (int l = 0; l < NQ; ++l) {
+            float4 q[3] = {make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0)};
+            if (need[l]) {
+                q[0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs0, (int)(zoff + col[l]), 0, 0));
+                q[1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs1, (int)(zoff + col[l]), 0, 0));
+                q[2] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs2, (int)(zoff + col[l]), 0, 0));
+            }
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                u[cc][4 * l + 0] = q[cc].x;
+                u[cc][4 * l + 1] = q[cc].y;
+                u[cc][4 * l + 2] = q[cc].z;
+                u[cc][4 * l + 3] = q[cc].w;
+            }
         }
         if (++z == Mz) {
             z = 0;
@@ -723,19 +726,21 @@ __global__ __launch_bounds__(256) void k_interp8(const GridRec<float>* __restric
         }
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
-            const float4 ua = u[cc][0], ub = u[cc][1];
-            const float pc = gw[0] * ua.x + gw[1] * ua.y + gw[2] * ua.z + gw[3] * ua.w +
-                             gw[4] * ub.x + gw[5] * ub.y + gw[6] * ub.z + gw[7] * ub.w;
-            const float rc = gwd2[0] * ua.x + gwd2[1] * ua.y + gwd2[2] * ua.z + gwd2[3] * ua.w +
-                             gwd2[4] * ub.x + gwd2[5] * ub.y + gwd2[6] * ub.z + gwd2[7] * ub.w;
+            float pc = 0.0f, rc = 0.0f;
+#pragma unroll
+            for (int t = 0; t < NX; ++t) {
+                pc += gw[t] * u[cc][t];
+                rc += gwd2[t] * u[cc][t];
+            }
             P[cc] += e.g * pc;
             Rr[cc] += e.g * rc;
             PD2[cc] += e.gd2 * pc;
             if (OMEGA) {
                 if (cc < 2) PD[cc] += e.gDd * pc;
                 if (cc > 0) {
-                    const float qc = gwd[0] * ua.x + gwd[1] * ua.y + gwd[2] * ua.z + gwd[3] * ua.w +
-                                     gwd[4] * ub.x + gwd[5] * ub.y + gwd[6] * ub.z + gwd[7] * ub.w;
+                    float qc = 0.0f;
+#pragma unroll
+                    for (int t = 0; t < NX; ++t) qc += gwd[t] * u[cc][t];
                     Q[cc - 1] += e.g * qc;
                 }
             }
@@ -852,17 +857,30 @@ hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W,
     dim3 g((unsigned)((P->N + 3) / 4)), b(256);
     const GridRec<R>* rec = (const GridRec<R>*)P->grec;
     if constexpr (sizeof(R) == sizeof(float)) {
-        if (P->M % 4 == 0 && P->MG <= 13 && a.same_width &&
+        // Packed kernels need quads of four x points (M divisible by 4) and one
+        // width.  In the tiled layout the two lanes of a support row read one
+        // 8 x 4 tile's halves per load, so several particles per wavefront pay
+        // (M_G <= 16); in the row-major layout rows are a plane row apart and
+        // only the four-lane form (M_G <= 13) reads few enough cache lines per
+        // byte to beat the one-column-per-lane kernel.
+        if (P->M % 4 == 0 && a.same_width && tiled && P->MG <= 16 &&
             (size_t)P->M * P->My * P->Mz <= (size_t)512 * 512 * 512) {
             const int ppw = std::min(4, 32 / P->MG);
             dim3 g8((unsigned)((P->N + 4 * ppw - 1) / (4 * ppw)));
-            if (W == nullptr)
-                hipLaunchKernelGGL(k_interp8<false>, g8, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
-            else
-                hipLaunchKernelGGL(k_interp8<true>, g8, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
+            if (P->MG <= 13) {
+                if (W == nullptr)
+                    hipLaunchKernelGGL((k_interp8<false, 2>), g8, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
+                else
+                    hipLaunchKernelGGL((k_interp8<true, 2>), g8, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
+            } else {
+                if (W == nullptr)
+                    hipLaunchKernelGGL((k_interp8<false, 3>), g8, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
+                else
+                    hipLaunchKernelGGL((k_interp8<true, 3>), g8, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
+            }
             return hipGetLastError();
         }
-        if (P->M % 4 == 0 && P->MG <= 13 && a.same_width) {
+        if (P->M % 4 == 0 && a.same_width && P->MG <= 13) {
             if (W == nullptr)
                 hipLaunchKernelGGL(k_interp4<false>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
             else
