@@ -1,7 +1,7 @@
 """Rectangular periodic boxes on the GPU (fcm_plan_box) against the oracle.
 
-Cases: a box long in x (48 x 18 x 18 points, M_G = 12: the packed FP32
-interpolation), a flat one (48 x 32 x 24, M_G = 16), and a thin one (64 x 64 x
+Cases: a box long in x (48 x 18 x 18 points, M_G = 12: the four-lane FP32
+interpolation of the row-major layout), a flat one (48 x 32 x 24, M_G = 16), and a thin one (64 x 64 x
 16, M_G = 16, so spreading tiles are one point high); every operator and the
 whole mobility, FP64 (1e-10 normwise) and FP32 bulk (1e-5).  Also the copy
 identity of the oracle's box pins, on the GPU: copies of a cube along one axis
