@@ -5,8 +5,9 @@
 //
 // The counting sort places particles with atomics and then orders every
 // segment by original index, so the sorted order is (key, original index):
-// deterministic from run to run.  Short segments are ordered by one thread
-// each; longer ones (dense bins, large pair cells) by a workgroup each.  With
+// deterministic from run to run.  Segments of up to 16 members are ordered by
+// one thread each (in registers), up to 64 by a wavefront, longer ones (dense
+// bins, large pair cells) by a workgroup each.  With
 // no pair search (R_c = 0) the pair order is the caller's order.  The records are built in the caller's
 // order (coalesced reads of positions, forces and torques) and stored at each
 // particle's sorted position through the inverse permutation.
@@ -30,8 +31,9 @@ struct HashArgs {
     double Lv[3], dx, cw[3];       // box sides, grid spacing, cell widths
 };
 
-constexpr int kShortSegment = 64;      // ordered by one thread
-constexpr int kLdsSegment = 8192;      // ordered by a bitonic sort in LDS
+constexpr int kThreadSegment = 16;     // ordered by one thread, in registers
+constexpr int kWaveSegment = 64;       // ordered by one wavefront
+constexpr int kLdsSegment = 8192;      // ordered by a workgroup's bitonic sort in LDS
 
 // wrap into [0, L); non-finite values, and values too large for the wrap to
 // land in [0, L), become 0 and raise the plan's flag.  Every index derived
@@ -81,6 +83,10 @@ __global__ void k_hash(const double* __restrict__ pos, HashArgs h, int* __restri
         c[a] = cc < 0 ? 0 : (cc >= h.mc[a] ? h.mc[a] - 1 : cc);
     }
     if (bad) atomicOr(flag, 1);
+    if (i == 0) {
+        flag[1] = 0;   // work-list lengths of the segment sorts
+        flag[2] = 0;
+    }
     int bin = s[0] / h.TX + h.nbx * (s[1] / h.TY + h.nby * (s[2] / h.TZ));
     int cell = c[0] + h.mc[0] * (c[1] + h.mc[1] * c[2]);
     keys[i] = bin;
@@ -220,48 +226,131 @@ __device__ inline void segment(int s, const int* starts, int nbins, int N, int* 
     *e = start[s + 1];
 }
 
+// n (2 <= n <= W) values of pm[b..b+n) sorted in registers by a bitonic
+// network over W entries (the rest padded with INT_MAX), written back with
+// the inverse permutation iv[pm[j]] = j
+template <int W>
+__device__ inline void thread_sort(int* pm, int* iv, int b, int n) {
+    int v[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) v[i] = i < n ? pm[b + i] : 0x7fffffff;
+#pragma unroll
+    for (int k = 2; k <= W; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int x = v[i], y = v[l];
+                    const bool up = (i & k) == 0;
+                    v[i] = up ? min(x, y) : max(x, y);
+                    v[l] = up ? max(x, y) : min(x, y);
+                }
+            }
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+        if (i < n) {
+            pm[b + i] = v[i];
+            iv[v[i]] = b + i;
+        }
+}
+
+// Append s to a work list with one atomic per wavefront (the lanes with
+// `want` set); list entries go to list[idx] (dir > 0) or list[-idx] (dir < 0).
+__device__ inline void wave_append(bool want, int s, int* counter, int* list, int dir) {
+    const unsigned long long m = __ballot(want);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (want) {
+        const int idx = base + __popcll(m & ((1ull << lane) - 1ull));
+        list[dir > 0 ? idx : -idx] = s;
+    }
+}
+
 // Order each segment of perm by value and record the inverse permutation
-// inv[perm[j]] = j.  A thread orders a short segment by insertion.  Longer
-// segments of the block's range are then ordered by the whole workgroup, one
-// after the other: up to kLdsSegment members by a bitonic sort in LDS, beyond
-// that by rank counting (a member's rank is the number of smaller members,
-// counted against a copy of the segment staged through LDS; tmp holds the
-// copy, indexed like perm).
+// inv[perm[j]] = j.  A thread orders a segment of up to kThreadSegment members
+// in registers.  Longer segments go to two work lists for k_segment_wide:
+// up to kWaveSegment members (one wavefront each), and beyond (one workgroup
+// each).  The lists live in `lists` (the bin and cell counts, all zero
+// between the scan and the next hash): wavefront entries from the front,
+// workgroup entries from the back (index cap - 1 - i); their lengths in
+// counters[0], counters[1] (cleared by the hash).
 __global__ __launch_bounds__(256) void k_segment_order(const int* __restrict__ starts, int nbins,
                                                        int nseg, int N, int* __restrict__ perm,
-                                                       int* __restrict__ inv, int* __restrict__ tmp) {
-    __shared__ int sh[kLdsSegment];
-    __shared__ int nlong;
-    __shared__ int longs[256];
-    const int t = threadIdx.x, nt = blockDim.x;
-    if (t == 0) nlong = 0;
-    __syncthreads();
-    const int s = blockIdx.x * blockDim.x + t;
+                                                       int* __restrict__ inv, int* __restrict__ lists,
+                                                       int cap, int* __restrict__ counters) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = 0;
     if (s < nseg) {
         int b, e;
         int *pm, *iv;
         segment(s, starts, nbins, N, perm, inv, &b, &e, &pm, &iv);
-        if (e - b > kShortSegment) {
-            longs[atomicAdd(&nlong, 1)] = s;
-        } else {
-            for (int i = b + 1; i < e; ++i) {
-                const int v = pm[i];
-                int j = i - 1;
-                while (j >= b && pm[j] > v) {
-                    pm[j + 1] = pm[j];
-                    --j;
-                }
-                pm[j + 1] = v;
-            }
-            for (int i = b; i < e; ++i) iv[pm[i]] = i;
+        n = e - b;
+        if (n == 1) {
+            iv[pm[b]] = b;
+        } else if (n > 1 && n <= 4) {
+            thread_sort<4>(pm, iv, b, n);
+        } else if (n > 4 && n <= kThreadSegment) {
+            thread_sort<kThreadSegment>(pm, iv, b, n);
         }
     }
-    __syncthreads();
-    const int count = nlong;
-    for (int q = 0; q < count; ++q) {
+    wave_append(n > kThreadSegment && n <= kWaveSegment, s, counters, lists, 1);
+    wave_append(n > kWaveSegment, s, counters + 1, lists + cap - 1, -1);
+}
+
+// The segments k_segment_order listed.  Wavefront items: a bitonic sort of
+// one value per lane by lane exchanges.  Workgroup items: up to kLdsSegment
+// members by a bitonic sort in LDS, beyond that by rank counting (a member's
+// rank is the number of smaller members, counted against a copy of the
+// segment staged through LDS; tmp holds the copy, indexed like perm).  Each
+// list entry is cleared once read, so the counts are zero again for the next
+// hash.
+__global__ __launch_bounds__(256) void k_segment_wide(const int* __restrict__ starts, int nbins,
+                                                      int N, int* __restrict__ perm,
+                                                      int* __restrict__ inv, int* __restrict__ tmp,
+                                                      int* __restrict__ lists, int cap,
+                                                      const int* __restrict__ counters) {
+    __shared__ int sh[kLdsSegment];
+    __shared__ int item;
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int lane = t & 63;
+    const int nwave = counters[0], nblock = counters[1];
+    const int waves = gridDim.x * (nt / 64);
+    for (int it = blockIdx.x * (nt / 64) + (t >> 6); it < nwave; it += waves) {
+        const int s = __builtin_amdgcn_readfirstlane(lists[it]);
+        if (lane == 0) lists[it] = 0;
         int b, e;
         int *pm, *iv;
-        segment(longs[q], starts, nbins, N, perm, inv, &b, &e, &pm, &iv);
+        segment(s, starts, nbins, N, perm, inv, &b, &e, &pm, &iv);
+        const int n = e - b;
+        int v = lane < n ? pm[b + lane] : 0x7fffffff;
+#pragma unroll
+        for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int o = __shfl_xor(v, j, 64);
+                const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+                v = (lower == up) ? min(v, o) : max(v, o);
+            }
+        if (lane < n) {
+            pm[b + lane] = v;
+            iv[v] = b + lane;
+        }
+    }
+    for (int it = blockIdx.x; it < nblock; it += gridDim.x) {
+        if (t == 0) {
+            item = lists[cap - 1 - it];
+            lists[cap - 1 - it] = 0;
+        }
+        __syncthreads();
+        int b, e;
+        int *pm, *iv;
+        segment(item, starts, nbins, N, perm, inv, &b, &e, &pm, &iv);
         const int n = e - b;
         if (n <= kLdsSegment) {
             int p2 = 1;
@@ -426,8 +515,12 @@ hipError_t launch_scatter(const fcm_plan_impl* P, hipStream_t st) {
     // (which runs after the records are built): it holds the copies of the
     // longest segments.
     const int nseg = P->nbins + (P->rc > 0.0 ? P->ncells : 0);
+    const int cap = P->nbins + P->cells_cap;   // entries of the counts array (>= nseg)
     hipLaunchKernelGGL(k_segment_order, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, P->starts,
-                       P->nbins, nseg, N, P->perm, P->ranks, P->pair_hits);
+                       P->nbins, nseg, N, P->perm, P->ranks, P->counts, cap, P->flag + 1);
+    const int wide = std::min(2048, std::max(1, nseg / 64));
+    hipLaunchKernelGGL(k_segment_wide, dim3(wide), dim3(256), 0, st, P->starts, P->nbins, N,
+                       P->perm, P->ranks, P->pair_hits, P->counts, cap, P->flag + 1);
     return hipGetLastError();
 }
 

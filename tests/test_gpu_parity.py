@@ -280,6 +280,58 @@ def test_long_sort_segments_match_oracle(prec):
     assert normwise(V1[sub], Vr) < tol and normwise(W1[sub], Wr) < tol
 
 
+def _mid_clusters(sizes=(3, 16, 17, 33, 64, 65, 300), n_rest=100, seed=12):
+    """Clusters of the given sizes, each inside one pair cell (width 2) and one
+    grid cell (dx = 1.25), so pair cells hold exactly those counts (loose
+    particles rarely join) across the thread (<= 16), wavefront (17..64) and
+    workgroup (> 64) sorts; grid bins (8 x 8 x 16 support starts) hold one or
+    two clusters."""
+    rng = np.random.default_rng(seed)
+    L, grid = 40.0, 32
+    corners = [(10, 10, 10), (20, 10, 10), (10, 20, 10), (10, 10, 20), (30, 10, 10), (20, 20, 20),
+               (30, 30, 30)]
+    parts = []
+    for n, c in zip(sizes, corners):
+        k = int(math.ceil(n ** (1.0 / 3.0)))
+        g = (np.stack(np.meshgrid(*([np.arange(k)] * 3), indexing="ij"), -1).reshape(-1, 3) + 0.5) / k
+        g = g[rng.choice(len(g), size=n, replace=False)]
+        parts.append(np.array(c) + 0.05 + 1.15 * g + rng.uniform(-0.2, 0.2, size=(n, 3)) * 1.15 / k)
+    parts.append(rng.uniform(0.0, L, size=(n_rest, 3)))
+    Y = np.concatenate(parts)
+    Y = Y[rng.permutation(len(Y))]
+    N = len(Y)
+    return dict(N=N, L=L, a=A, eta=1.0, grid=grid, Sigma=1.5 * SIG, M_G=12, R_c=2.0,
+                Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mid_sort_segments_match_oracle(prec):
+    """Pair cells of 3, 16, 17, 33, 64, 65 and 300 members (both sides of the
+    thread/wavefront and wavefront/workgroup limits of the segment sorts):
+    spread and the mobility of every cluster's members agree with the oracle,
+    repeated calls are bitwise equal, and a permuted input gives the permuted
+    result."""
+    w = _mid_clusters()
+    p = oracle_params(w)
+    plan = make_plan(w, PREC[prec][0])
+    Y, F, T = dev(w["Y"]), dev(w["F"]), dev(w["T"])
+    f = ff.spread(p, w["Y"], w["F"], w["T"])
+    tol = PREC[prec][1]
+    assert normwise(gpu_to_oracle_grid(host(plan.spread(Y, F, T))), f) < tol
+    V1, W1 = plan.mobility(Y, F, T)
+    V2, W2 = plan.mobility(Y, F, T)
+    V1, W1 = host(V1), host(W1)
+    assert np.array_equal(V1, host(V2)) and np.array_equal(W1, host(W2))
+    sub = np.sort(np.random.default_rng(4).choice(w["N"], size=80, replace=False))
+    Vr, Wr = ff.mobility(p, w["Y"], w["F"], w["T"], targets=sub)
+    tol_m = 1e-9 if prec == "fp64" else 1e-5
+    assert normwise(V1[sub], Vr) < tol_m and normwise(W1[sub], Wr) < tol_m
+    perm = np.random.default_rng(6).permutation(w["N"])
+    V3, W3 = plan.mobility(dev(w["Y"][perm]), dev(w["F"][perm]), dev(w["T"][perm]))
+    tol_p = 1e-12 if prec == "fp64" else 1e-5
+    assert maxrel(host(V3), V1[perm]) < tol_p and maxrel(host(W3), W1[perm]) < tol_p
+
+
 def test_standard_fcm_widths_recognised():
     """Standard FCM passed with the torque width rounded differently (one part
     in 1e14) is recognised as such: no correction, results equal to those of
