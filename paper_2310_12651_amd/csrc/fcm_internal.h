@@ -14,7 +14,7 @@ constexpr int kMaxRadixStages = 16;
 constexpr int kMaxSupport = 32;      // largest M_G accepted
 constexpr int kMaxGrid = 1024;       // largest grid per axis accepted
 constexpr int kMaxCellsPerAxis = 128;
-constexpr int kPairCap = 16;         // neighbours recorded per (particle, z layer)
+constexpr int kPairCap = 48;         // neighbours recorded per (particle, z layer)
 
 template <typename R>
 struct C2 {
