@@ -109,6 +109,12 @@ void choose_tiles(fcm_plan_impl* P) {
             P->TZ = t;
             break;
         }
+    // One wavefront spreads a tile: with fewer than 8 tiles per SIMD (8192 on
+    // the 1024 SIMDs) latency and crowded tiles are poorly hidden, and tiles
+    // of height 8 pay less than their extra candidate scans (measured: 192^3
+    // clustered rods and 128^3 dilute faster, 256^3 dense slower).
+    if (P->TZ > 8 && Mz % 8 == 0 && (int64_t)(M / P->TX) * (My / P->TY) * (Mz / P->TZ) < 8192)
+        P->TZ = 8;
     P->nbx = M / P->TX;
     P->nby = My / P->TY;
     P->nbz = Mz / P->TZ;
