@@ -16,9 +16,12 @@
 // each lane forms its (x, y) column factors once per particle and then needs
 // only a few FMAs per z point.
 //
-// Interpolation is particle-major: one wavefront per particle, lanes over the
-// (x, y) columns of the M_G^3 support, a factorised sum along z per lane, and
-// a butterfly shuffle reduction across the wavefront.
+// Interpolation is particle-major, with a factorised sum along z per lane: in
+// general one wavefront per particle with lanes over the (x, y) columns of the
+// M_G^3 support and a butterfly shuffle reduction; in FP32 with one width,
+// lanes over support rows reading 16-byte quads of four x points (k_interp4:
+// one particle a wavefront; k_interp8: several, for fields in the tiled
+// layout).
 #include "fcm_internal.h"
 
 namespace fcm {
