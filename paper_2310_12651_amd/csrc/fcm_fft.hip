@@ -753,69 +753,77 @@ __global__ __launch_bounds__((XGeom<N1, N2>::NT)) void k_fft_x_c2r_reg(float* __
 }
 
 
-// ---- x and y passes fused over one (component, z) plane (M = 256, FP32) ----
+// ---- x and y passes fused over one (component, z) plane (FP32) ----
 //
-// A 1024-thread workgroup holds a whole 256 x 256 plane in registers (64
-// floats a thread) and does both in-plane transforms before writing it back,
-// so the plane crosses HBM once each way instead of twice.  Forward: the x
-// transforms of the 256 lines in two rounds of 128 (8 threads a line: the
-// register four-step and the real/complex split of the x pass), a transpose
-// through LDS in two halves of 64 kx columns, and the y transforms of those
-// columns (16 threads a column: the register four-step of the y pass); the
-// inverse runs the same steps backwards.  The x exchange (128 lines), the
-// transpose (256 rows of 64 columns) and the y exchange (64 columns) take
-// turns in one LDS buffer; the row strides put the lines or rows one
-// wavefront touches at once in different banks.
-namespace xy {
-constexpr int M = 256, H = 128;
-constexpr int XN1 = 16, XN2 = 8, T = 8;  // x: H = 16 x 8, 8 threads a line
-constexpr int YN1 = 16, YN2 = 16;        // y: M = 16 x 16, 16 threads a column
-constexpr int NT = 1024;
-constexpr int LR = NT / T;               // lines per x round
-constexpr int KS = XN2 + 1;              // x exchange: k1 stride (complex)
-constexpr int LS = 152;                  // x exchange: line stride
-constexpr int CW = NT / YN2;             // kx columns per y round
-constexpr int RS = CW + 8;               // transpose: row stride
-constexpr int PL = YN2 * CW + 8;         // y exchange: k1 stride
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int LDSN = cmax(LR * LS, cmax(M * RS, YN1 * PL));
-static_assert(XN1 * XN2 == H && YN1 * YN2 == M && LR * 2 == M && CW * 2 == H, "plane geometry");
-static_assert(KS * (XN1 - 1) + XN2 <= LS, "x exchange fits a line");
-static_assert((LDSN + M) * 8 <= 163840, "LDS of one workgroup");
-static_assert(XGeom<XN1, XN2>::SHFL, "x partners by lane shuffles");
-}  // namespace xy
+// A workgroup holds a whole M x M plane in registers and does both in-plane
+// transforms before writing it back, so the plane crosses HBM once each way
+// instead of twice.  Forward: the x transforms of the M lines in RX rounds of
+// LR (T threads a line: the register four-step and the real/complex split of
+// the x pass), then the H kx columns in RY rounds of CW: each round's columns
+// are transposed through LDS and transformed by YN2 threads a column (the
+// register four-step of the y pass); the inverse runs the same steps
+// backwards.  The x exchange, the transpose and the y exchange take turns in
+// one LDS buffer; their strides put the lines or rows one wavefront writes at
+// different bank offsets.  Sizes: 64, 96, 128 and 256 (whose x geometry
+// exchanges partners by lane shuffles and whose plane fits one workgroup).
+template <int M_, int XN1_, int XN2_, int YN1_, int YN2_, int NT_>
+struct XYGeom {
+    static constexpr int M = M_, H = M_ / 2, XN1 = XN1_, XN2 = XN2_, T = XN2_;
+    static constexpr int YN1 = YN1_, YN2 = YN2_, NT = NT_;
+    static constexpr int LR = NT / T, RX = M / LR;   // x: lines per round, rounds
+    static constexpr int CW = NT / YN2, RY = H / CW;  // y: kx columns per round, rounds
+    static constexpr int KS = XN2 + 1;               // x exchange: k1 stride (complex)
+    // the smallest stride >= need that is congruent to r modulo 32 complex
+    static constexpr int up_to(int need, int r) { return need + ((r - need % 32) % 32 + 32) % 32; }
+    static constexpr int LS = up_to(KS * (XN1 - 1) + XN2, (3 * T) % 32);  // x exchange: line stride
+    static constexpr int RS = up_to(CW, T % 32);                          // transpose: row stride
+    static constexpr int PL = YN2 * CW + 8;                                // y exchange: k1 stride
+    static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+    static constexpr int LDSN = cmax(LR * LS, cmax(M * RS, YN1 * PL));
+    static_assert(XN1 * XN2 == H && YN1 * YN2 == M, "factorisations of the plane");
+    static_assert(XN1 % XN2 == 0 && YN1 % YN2 == 0, "four-step: N2 divides N1");
+    static_assert(LR * RX == M && CW * RY == H && CW % T == 0, "rounds cover the plane");
+    static_assert(XGeom<XN1, XN2>::SHFL, "x partners by lane shuffles");
+    static_assert((LDSN + M) * 8 <= 163840, "LDS of one workgroup");
+};
 
-// element x (even) of line y of a plane: its pair of reals (x, x + 1)
-template <bool TILED>
-__device__ inline C2<float>* xy_pair(float* pg, int y, int x) {
-    if (TILED)
-        return reinterpret_cast<C2<float>*>(pg + (y >> 2) * (xy::M << 2) + ((y & 3) << 3) +
-                                            ((x >> 3) << 5) + (x & 7));
-    return reinterpret_cast<C2<float>*>(pg + y * xy::M + x);
+// threads of the fused passes for an M x M plane (0: separate passes)
+constexpr int fused_xy_threads(int M) {
+    return M == 64 ? 256 : M == 96 ? 192 : M == 128 ? 512 : M == 256 ? 1024 : 0;
 }
 
-template <bool TILED>
-__global__ __launch_bounds__(1024) void k_fft_xy_r2c(float* __restrict__ grid,
+// element x (even) of line y of a plane: its pair of reals (x, x + 1)
+template <int M, bool TILED>
+__device__ inline C2<float>* xy_pair(float* pg, int y, int x) {
+    if (TILED)
+        return reinterpret_cast<C2<float>*>(pg + (y >> 2) * (M << 2) + ((y & 3) << 3) +
+                                            ((x >> 3) << 5) + (x & 7));
+    return reinterpret_cast<C2<float>*>(pg + y * M + x);
+}
+
+template <class G, bool TILED>
+__global__ __launch_bounds__(G::NT) void k_fft_xy_r2c(float* __restrict__ grid,
                                                      const C2<float>* __restrict__ twg) {
-    using namespace xy;
+    constexpr int M = G::M, H = G::H, XN1 = G::XN1, XN2 = G::XN2, T = G::T, YN1 = G::YN1;
+    constexpr int YN2 = G::YN2, NT = G::NT, LR = G::LR, RX = G::RX, CW = G::CW, RY = G::RY;
     __shared__ C2<float> tw[M];
-    __shared__ C2<float> E[LDSN];
+    __shared__ C2<float> E[G::LDSN];
     const int plane = xcd_remap(blockIdx.x, gridDim.x);  // component * M + z
     const int tid = threadIdx.x;
     float* pg = grid + (size_t)plane * M * M;
     C2<float>* spec = reinterpret_cast<C2<float>*>(pg);   // the plane's M x H spectrum
     for (int e = tid; e < M; e += NT) tw[e] = twg[e];
-    // x: thread (ll, q) holds lines ll and ll + LR, elements q + T j of each
+    // x: thread (ll, q) holds lines ll + LR r, elements q + T j of each
     const int q = tid % T, ll = tid / T;
-    C2<float> v[2][XN1];
+    C2<float> v[RX][XN1];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < RX; ++r)
 #pragma unroll
-        for (int j = 0; j < XN1; ++j) v[r][j] = *xy_pair<TILED>(pg, ll + LR * r, 2 * (j * T + q));
+        for (int j = 0; j < XN1; ++j) v[r][j] = *xy_pair<M, TILED>(pg, ll + LR * r, 2 * (j * T + q));
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        four_step<XN1, XN2, -1, 2>(v[r], tw, E + ll * LS, q, KS, 1);
+    for (int r = 0; r < RX; ++r) {
+        four_step<XN1, XN2, -1, 2>(v[r], tw, E + ll * G::LS, q, G::KS, 1);
         C2<float> pv[XN1];
         x_partners<XN1, XN2>(v[r], pv, nullptr, q);
         // X_k = (Z_k + conj Z_{H-k})/2 - (i/2) exp(-2 pi i k/M) (Z_k - conj Z_{H-k})
@@ -831,57 +839,58 @@ __global__ __launch_bounds__(1024) void k_fft_xy_r2c(float* __restrict__ grid,
     // y: thread (p, w) transforms column CW h + w, elements p + YN2 j
     const int w = tid % CW, p = tid / CW;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < RY; ++h) {
         // kx = q + T i lies in [CW h, CW h + CW) for i = (CW / T) h + ii
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < RX; ++r)
 #pragma unroll
-            for (int ii = 0; ii < CW / T; ++ii) E[(ll + LR * r) * RS + q + T * ii] = v[r][(CW / T) * h + ii];
+            for (int ii = 0; ii < CW / T; ++ii) E[(ll + LR * r) * G::RS + q + T * ii] = v[r][(CW / T) * h + ii];
         __syncthreads();
         C2<float> u[YN1];
 #pragma unroll
-        for (int j = 0; j < YN1; ++j) u[j] = E[(p + YN2 * j) * RS + w];
+        for (int j = 0; j < YN1; ++j) u[j] = E[(p + YN2 * j) * G::RS + w];
         __syncthreads();
-        four_step<YN1, YN2, -1, 1>(u, tw, E + w, p, PL, CW);
+        four_step<YN1, YN2, -1, 1>(u, tw, E + w, p, G::PL, CW);
 #pragma unroll
         for (int i = 0; i < YN1; ++i) spec[(p + YN2 * i) * H + CW * h + w] = u[i];
     }
 }
 
-template <bool TILED>
-__global__ __launch_bounds__(1024) void k_fft_xy_c2r(float* __restrict__ grid,
+template <class G, bool TILED>
+__global__ __launch_bounds__(G::NT) void k_fft_xy_c2r(float* __restrict__ grid,
                                                      const C2<float>* __restrict__ twg) {
-    using namespace xy;
+    constexpr int M = G::M, H = G::H, XN1 = G::XN1, XN2 = G::XN2, T = G::T, YN1 = G::YN1;
+    constexpr int YN2 = G::YN2, NT = G::NT, LR = G::LR, RX = G::RX, CW = G::CW, RY = G::RY;
     __shared__ C2<float> tw[M];
-    __shared__ C2<float> E[LDSN];
+    __shared__ C2<float> E[G::LDSN];
     const int plane = xcd_remap(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
     float* pg = grid + (size_t)plane * M * M;
     const C2<float>* spec = reinterpret_cast<const C2<float>*>(pg);
     for (int e = tid; e < M; e += NT) tw[e] = twg[e];
     const int w = tid % CW, p = tid / CW;
-    C2<float> u[2][YN1];
+    C2<float> u[RY][YN1];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < RY; ++h)
 #pragma unroll
         for (int j = 0; j < YN1; ++j) u[h][j] = spec[(p + YN2 * j) * H + CW * h + w];
     __syncthreads();
     const int q = tid % T, ll = tid / T;
-    C2<float> x[2][XN1];
+    C2<float> x[RX][XN1];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        four_step<YN1, YN2, 1, 1>(u[h], tw, E + w, p, PL, CW);
+    for (int h = 0; h < RY; ++h) {
+        four_step<YN1, YN2, 1, 1>(u[h], tw, E + w, p, G::PL, CW);
 #pragma unroll
-        for (int i = 0; i < YN1; ++i) E[(p + YN2 * i) * RS + w] = u[h][i];
+        for (int i = 0; i < YN1; ++i) E[(p + YN2 * i) * G::RS + w] = u[h][i];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < RX; ++r)
 #pragma unroll
-            for (int ii = 0; ii < CW / T; ++ii) x[r][(CW / T) * h + ii] = E[(ll + LR * r) * RS + q + T * ii];
+            for (int ii = 0; ii < CW / T; ++ii) x[r][(CW / T) * h + ii] = E[(ll + LR * r) * G::RS + q + T * ii];
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < RX; ++r) {
         // Z_k = E + i O, E = X_k + conj X_{H-k}, O = exp(+2 pi i k/M) (X_k - conj X_{H-k}),
         // with the x-Nyquist coefficient X_H taken as 0
         C2<float> pv[XN1];
@@ -897,9 +906,9 @@ __global__ __launch_bounds__(1024) void k_fft_xy_c2r(float* __restrict__ grid,
             const C2<float> O = cmul(csub(x[r][i], Xc), wk);
             x[r][i] = C2<float>{Ev.x - O.y, Ev.y + O.x};
         }
-        four_step<XN1, XN2, 1, 2>(x[r], tw, E + ll * LS, q, KS, 1);
+        four_step<XN1, XN2, 1, 2>(x[r], tw, E + ll * G::LS, q, G::KS, 1);
 #pragma unroll
-        for (int i = 0; i < XN1; ++i) *xy_pair<TILED>(pg, ll + LR * r, 2 * (q + T * i)) = x[r][i];
+        for (int i = 0; i < XN1; ++i) *xy_pair<M, TILED>(pg, ll + LR * r, 2 * (q + T * i)) = x[r][i];
     }
 }
 
@@ -942,15 +951,17 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     const int nlines = 3 * M * M;
     const dim3 gx((nlines + X::LPB - 1) / X::LPB), bx(X::NT);
     const bool tl = tiled && M % 8 == 0;
-    // M = 256: the x and y passes of a plane in one workgroup (stage times: the
-    // fused pass is reported as the x pass, the y pass as empty)
-    constexpr bool fused = M == xy::M && XN1 == xy::XN1 && YN1 == xy::YN1;
+    // the x and y passes of a plane in one workgroup where it fits (stage
+    // times: the fused pass is reported as the x pass, the y pass as empty)
+    constexpr int FNT = fused_xy_threads(M);
+    constexpr bool fused = FNT > 0;
+    using XY = XYGeom<M, XN1, XN2, YN1, YN2, fused ? FNT : 2 * M>;
     mark(0);
     if constexpr (fused) {
         if (tl)
-            hipLaunchKernelGGL(k_fft_xy_r2c<true>, dim3(3 * M), dim3(xy::NT), 0, st, grid, tw);
+            hipLaunchKernelGGL((k_fft_xy_r2c<XY, true>), dim3(3 * M), dim3(FNT), 0, st, grid, tw);
         else
-            hipLaunchKernelGGL(k_fft_xy_r2c<false>, dim3(3 * M), dim3(xy::NT), 0, st, grid, tw);
+            hipLaunchKernelGGL((k_fft_xy_r2c<XY, false>), dim3(3 * M), dim3(FNT), 0, st, grid, tw);
         mark(1);
     } else {
         if (tl)
@@ -971,9 +982,9 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     if constexpr (fused) {
         mark(4);
         if (tl)
-            hipLaunchKernelGGL(k_fft_xy_c2r<true>, dim3(3 * M), dim3(xy::NT), 0, st, grid, tw);
+            hipLaunchKernelGGL((k_fft_xy_c2r<XY, true>), dim3(3 * M), dim3(FNT), 0, st, grid, tw);
         else
-            hipLaunchKernelGGL(k_fft_xy_c2r<false>, dim3(3 * M), dim3(xy::NT), 0, st, grid, tw);
+            hipLaunchKernelGGL((k_fft_xy_c2r<XY, false>), dim3(3 * M), dim3(FNT), 0, st, grid, tw);
     } else {
         hipLaunchKernelGGL((k_fft_y_reg<YN1, YN2, YW, 1>), dim3(Y::NG * 3 * M), dim3(Y::NT), 0, st,
                            spec, tw);
