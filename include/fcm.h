@@ -197,7 +197,11 @@ int fcm_plan_footprint(int64_t N, int grid, int precision, int64_t* bytes);
 int fcm_plan_last_error(fcm_plan_t p);
 /*
  * Per-stage timing with HIP events.  When enabled, every fcm_mobility call records
- * its stage boundaries (up to 1024 calls are kept); fcm_plan_stage_times
+ * its stage boundaries (up to 1024 calls are kept): enable = 1 times every stage,
+ * enable = 2 + s only stage s (three events a call instead of twelve, so the other
+ * stages run without the events' gaps; the untimed stages read 0), enable = 0
+ * stops; other values give FCM_EINVAL.  Changing the mode clears the record, so
+ * read it first.  fcm_plan_stage_times
  * synchronises, adds the elapsed milliseconds of each stage over the recorded
  * calls into ms_out[0..FCM_NUM_STAGES), stores the number of calls in *ncalls, and
  * clears the record.  Stages, in order: sort (hash, scan, scatter, records),

@@ -5,10 +5,10 @@ include/fcm.h); this package is its thin Python binding.
 """
 
 from ._lib import (FCM_EDEVICE, FCM_EINVAL, FCM_ENOMEM, FCM_ENONFINITE, FCM_ERANGE, FCM_FP32_BULK,
-                   FCM_FP64, FCM_OK, EXPORTS, FCMError, LibraryMissing, Options, Plan,
+                   FCM_FP64, FCM_OK, EXPORTS, STAGES, FCMError, LibraryMissing, Options, Plan,
                    fcm_options_default, fcm_plan_footprint, library, status_string, LIB_PATH)
 
 __all__ = ["Plan", "FCMError", "LibraryMissing", "Options", "library", "status_string",
            "fcm_options_default", "fcm_plan_footprint", "FCM_FP64", "FCM_FP32_BULK", "FCM_OK",
            "FCM_EINVAL", "FCM_ENOMEM", "FCM_EDEVICE", "FCM_ERANGE", "FCM_ENONFINITE", "EXPORTS",
-           "LIB_PATH"]
+           "LIB_PATH", "STAGES"]

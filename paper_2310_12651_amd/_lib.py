@@ -280,8 +280,11 @@ class Plan:
                "fcm_correct")
         return V, Omega
 
-    def set_timing(self, enable=True):
-        _check(library().fcm_plan_set_timing(self.handle, int(bool(enable))), "fcm_plan_set_timing")
+    def set_timing(self, enable=True, stage=None):
+        """Per-stage HIP-event timing of later calls: every stage, or with
+        `stage` (a name of STAGES) that stage alone."""
+        mode = 0 if not enable else (1 if stage is None else 2 + STAGES.index(stage))
+        _check(library().fcm_plan_set_timing(self.handle, mode), "fcm_plan_set_timing")
 
     def stage_times(self):
         """Per-stage milliseconds summed over the calls recorded since the last read."""

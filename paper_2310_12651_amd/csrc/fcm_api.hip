@@ -532,13 +532,13 @@ hipError_t mobility_from_records(fcm_plan_impl* p, const double* T, double* V, d
     if (corr) {
         e = hipEventRecord(p->fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
-        if (ev && e == hipSuccess) (void)hipEventRecord(ev[10], p->side);
+        if (ev && e == hipSuccess && timing_event(p, 10)) (void)hipEventRecord(ev[10], p->side);
         if (e == hipSuccess)
             e = launch_pair(p, p->corr, Omega ? p->corr + 3 * p->N : nullptr, T != nullptr, p->side,
                             true, scan);
-        if (ev && e == hipSuccess) (void)hipEventRecord(ev[11], p->side);
+        if (ev && e == hipSuccess && timing_event(p, 11)) (void)hipEventRecord(ev[11], p->side);
         if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
-    } else if (ev) {
+    } else if (ev && timing_event(p, 10)) {
         (void)hipEventRecord(ev[10], st);
         (void)hipEventRecord(ev[11], st);
     }
@@ -562,7 +562,7 @@ int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double*
     p->last_stream = st;
     hipEvent_t* ev = call_events(p);
     auto mark = [&](int i) {
-        if (ev) (void)hipEventRecord(ev[i], st);
+        if (ev && timing_event(p, i)) (void)hipEventRecord(ev[i], st);
     };
     mark(0);
     const bool corr = needs_correction(p);
@@ -587,7 +587,7 @@ int fcm_mobility_repeat(fcm_plan_t p, const double* F, const double* T, double* 
     p->last_stream = st;
     hipEvent_t* ev = call_events(p);
     auto mark = [&](int i) {
-        if (ev) (void)hipEventRecord(ev[i], st);
+        if (ev && timing_event(p, i)) (void)hipEventRecord(ev[i], st);
     };
     mark(0);
     const bool corr = needs_correction(p);
@@ -656,7 +656,7 @@ int fcm_brownian(fcm_plan_t p, const double* pos, const void* xi_grid, const dou
 }
 
 int fcm_plan_set_timing(fcm_plan_t p, int enable) {
-    if (!p) return FCM_EINVAL;
+    if (!p || enable < 0 || enable >= 2 + FCM_NUM_STAGES) return FCM_EINVAL;
     DeviceGuard g(p->device);
     if (enable && !p->events) {
         const int n = kMaxTimedCalls * kEvPerCall;
@@ -671,7 +671,7 @@ int fcm_plan_set_timing(fcm_plan_t p, int enable) {
             }
         }
     }
-    p->timing = enable ? 1 : 0;
+    p->timing = enable;
     p->ev_calls = 0;
     return FCM_OK;
 }
@@ -690,6 +690,7 @@ int fcm_plan_stage_times(fcm_plan_t p, double* ms_out, int* ncalls) {
         for (int s = 0; s < FCM_NUM_STAGES; ++s) {
             // the pair correction (last stage) is timed on the side stream
             const int b = s == FCM_NUM_STAGES - 1 ? 10 : s, t = s == FCM_NUM_STAGES - 1 ? 11 : s + 1;
+            if (!timing_event(p, b) || !timing_event(p, t)) continue;   // stage not timed
             float ms = 0.0f;
             hipError_t e = hipEventElapsedTime(&ms, ev[b], ev[t]);
             if (e != hipSuccess) return map_err(e);

@@ -943,7 +943,7 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     using Y = ColGeom<YN1, YN2, YW>;
     static_assert(2 * X::H == Y::M, "x and y factorisations of the same M");
     auto mark = [&](int i) {
-        if (ev) (void)hipEventRecord(ev[i], st);
+        if (ev && timing_event(P, i + 2)) (void)hipEventRecord(ev[i], st);
     };
     constexpr int M = Y::M;
     const C2<float>* tw = (const C2<float>*)P->twid;
@@ -1041,7 +1041,7 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
 #undef FCM_REG_CASE
     }
     auto mark = [&](int i) {
-        if (ev) (void)hipEventRecord(ev[i], st);
+        if (ev && timing_event(P, i + 2)) (void)hipEventRecord(ev[i], st);
     };
     const int M = P->M, H = P->H, My = P->My, Mz = P->Mz;
     // twiddle tables of lengths M, My, Mz, one after the other

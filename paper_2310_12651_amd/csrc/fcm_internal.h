@@ -171,11 +171,24 @@ struct fcm_plan_impl {
     int repeat_ok;         // the sorted records and pair lists belong to the last
                            // fcm_mobility's positions (fcm_mobility_repeat may run)
     // per-stage timing
-    int timing;
+    int timing;             // 0 off, 1 every stage, 2 + s stage s only
     int ev_calls;           // calls recorded
     int ev_cap;             // event sets allocated
     hipEvent_t* events;     // ev_cap * (FCM_NUM_STAGES + 1)
 };
+
+// Whether event i of a timed call is recorded.  Events 0..8 are the stage
+// boundaries on the call's stream (stage s runs from event s to s + 1), 9 the
+// end of the call, 10 and 11 the start and end of the pair correction on the
+// side stream (the last stage).  Timing mode 1 records all of them; mode 2 + s
+// only stage s's two and the end, so that a call timed for one kernel carries
+// three events instead of twelve.
+inline bool timing_event(const fcm_plan_impl* P, int i) {
+    if (P->timing <= 1 || i == 9) return true;
+    const int s = P->timing - 2;
+    if (s == 8) return i == 10 || i == 11;
+    return i == s || i == s + 1;
+}
 
 // ---- launchers (each enqueues on `st`; return hipError_t of the launch) ----
 namespace fcm {
