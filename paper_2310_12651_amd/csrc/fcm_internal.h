@@ -117,6 +117,10 @@ struct PairArgs {
     // the six Gaussian widths of the corrections: squared width s, erfc
     // argument scale 1/sqrt(2 s), exponent scale -1/(2 s), norm (2 pi s)^(-3/2)
     double wsq[6], escale[6], gexp[6], gnorm[6];
+    // constants of the correction blocks (d = sigma^2 - Sigma^2, s2 = 2 Sigma^2,
+    // sb = Sigma^2 + Sigma_D^2): 1/(8 pi eta), 1/(2 eta), d/eta, d^2/(4 eta s2),
+    // d/(4 eta sb), 1/s2
+    double c8, ch, deta, cq, cfb, is2;
 };
 
 }  // namespace fcm
@@ -165,7 +169,7 @@ struct fcm_plan_impl {
     double* partial;       // 1024 partial sums of the vector reductions
     hipStream_t side;      // the pair correction runs here, beside spread and FFT
     hipEvent_t fork, join; // sorted records ready / corrections ready
-    int* flag;             // [0] = non-finite position seen
+    int* flag;             // [0] non-finite position seen; [1], [2] segment-sort work-list lengths
     hipStream_t last_stream;
     int counts_dirty;      // counts may be non-zero (cleared by the next sort)
     int repeat_ok;         // the sorted records and pair lists belong to the last

@@ -46,11 +46,9 @@ struct Coef {
 };
 
 template <bool SAME>
-__device__ inline Coef correction_coeffs(double r, const PairArgs& a) {
+__device__ inline Coef correction_coeffs(double r, double ir, const PairArgs& a) {
     const double pi = 3.14159265358979323846;
-    const double eta = a.eta;
-    const double r2 = r * r, r3 = r2 * r;
-    const double d = a.sigma * a.sigma - a.Sigma * a.Sigma;
+    const double r2 = r * r, ir2 = ir * ir;
     auto E = [&](int w) { return erfc(r * a.escale[w]); };
     auto D = [&](int w) { return a.gnorm[w] * exp(r2 * a.gexp[w]); };
     const double E2 = E(W2), D2 = D(W2);
@@ -58,13 +56,13 @@ __device__ inline Coef correction_coeffs(double r, const PairArgs& a) {
     const double Ed = SAME ? E2 : E(WD), Dd = SAME ? D2 : D(WD);
     const double s1 = a.wsq[W1], s2 = a.wsq[W2], sa = a.wsq[WA], sb = a.wsq[WB];
     const double sc = a.wsq[WC], sd = a.wsq[WD];
-    const double i8 = 1.0 / (8.0 * pi * eta * r3);
-    const double ih = 1.0 / (2.0 * eta * r2);
+    const double i8 = a.c8 * ir2 * ir;  // 1 / (8 pi eta r^3)
+    const double ih = a.ch * ir2;       // 1 / (2 eta r^2)
     Coef c;
     // force-velocity: erf part = (E(r; sigma sqrt2) - E(r; Sigma sqrt2)) (G + sigma^2 lap G)
     {
         const double dE = E2 - E(W1);
-        const double g1 = 1.0 / (8.0 * pi * eta * r);
+        const double g1 = a.c8 * ir;                     // 1 / (8 pi eta r)
         const double g3 = 2.0 * a.sigma * a.sigma * i8;  // sigma^2 / (4 pi eta r^3)
         c.Avf = dE * (g1 + g3);
         c.Bvf = dE * (g1 - 3.0 * g3);
@@ -74,18 +72,19 @@ __device__ inline Coef correction_coeffs(double r, const PairArgs& a) {
         c.Avf += -t3;
         c.Bvf += 3.0 * t3;
         // -(sigma^2 - Sigma^2) Q2(s2), Q2 = -(1/eta)[(1 + s^2/r^2) I - (1 + 3 s^2/r^2) xh xh] Delta
-        c.Avf += d / eta * (1.0 + s2 / r2) * D2;
-        c.Bvf += -d / eta * (1.0 + 3.0 * s2 / r2) * D2;
+        c.Avf += a.deta * (1.0 + s2 * ir2) * D2;
+        c.Bvf += -a.deta * (1.0 + 3.0 * s2 * ir2) * D2;
         // -(sigma^2 - Sigma^2)^2 / 4 T(s2), T = (1/eta s^2)[(2 - r^2/s^2) I + (r^2/s^2) xh xh] Delta
-        const double tq = d * d / (4.0 * eta * s2) * D2;
-        c.Avf += -tq * (2.0 - r2 / s2);
-        c.Bvf += -tq * (r2 / s2);
+        const double tq = a.cq * D2;
+        const double rs = r2 * a.is2;
+        c.Avf += -tq * (2.0 - rs);
+        c.Bvf += -tq * rs;
     }
     // rotation-force: R(sa) - R(sb) - (d/2) K(sb)
     {
         const double dE = Eb - E(WA);
         const double Da = D(WA);
-        c.fof = (dE - 4.0 * pi * r * (sa * Da - sb * Db)) * i8 + d * Db / (4.0 * eta * sb);
+        c.fof = (dE - 4.0 * pi * r * (sa * Da - sb * Db)) * i8 + a.cfb * Db;
     }
     // rotation-torque: (P(sigma_D sqrt2) - P(Sigma_D sqrt2)) / 2
     {
@@ -119,8 +118,9 @@ __device__ inline void add_pair(double x0, double x1, double x2, double r2, cons
         w[2] += a.selfOT * T2;
         return;
     }
-    const Coef c = correction_coeffs<SAME>(r, a);
-    const double h0 = x0 / r, h1 = x1 / r, h2 = x2 / r;
+    const double ir = 1.0 / r;
+    const Coef c = correction_coeffs<SAME>(r, ir, a);
+    const double h0 = x0 * ir, h1 = x1 * ir, h2 = x2 * ir;
     const double hF = h0 * F0 + h1 * F1 + h2 * F2;
     const double hT = h0 * T0 + h1 * T1 + h2 * T2;
     // V += Avf F + Bvf xh (xh.F) + fof (T x x)
@@ -391,6 +391,13 @@ hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torq
         a.gexp[k] = -0.5 / wsq[k];
         a.gnorm[k] = pow(2.0 * pi * wsq[k], -1.5);
     }
+    const double d = sg2 - Sg2;
+    a.c8 = 1.0 / (8.0 * pi * a.eta);
+    a.ch = 1.0 / (2.0 * a.eta);
+    a.deta = d / a.eta;
+    a.cq = d * d / (4.0 * a.eta * wsq[1]);
+    a.cfb = d / (4.0 * a.eta * wsq[3]);
+    a.is2 = 1.0 / wsq[1];
     const dim3 ge((a.N + kPairPerBlock - 1) / kPairPerBlock), be(kPairBlock);
     if (P->SigmaD == P->Sigma)
         hipLaunchKernelGGL(k_pair_eval<true>, ge, be, 0, st, P->ppos, P->prec, cs, P->pair_hits,
