@@ -154,7 +154,9 @@ int fcm_mobility_repeat(fcm_plan_t p, const double* F, const double* T, double* 
  *   tol     : Lanczos stops when the relative change of the pair part is below tol.
  *   V       : device N x 3 FP64, overwritten.  iterations: host, Lanczos steps taken.
  * The caller supplies every random number, so results are reproducible.  The
- * Lanczos recurrence synchronises the stream at each step.  Requires
+ * Lanczos recurrence runs on the plan's second stream and the host waits for it
+ * at each step (the call returns when it has converged); the grid part runs on
+ * `stream` meanwhile, and V is complete in stream order.  Requires
  * fcm_brownian_reserve first when a correction is needed (FCM_EINVAL otherwise).
  */
 int fcm_brownian(fcm_plan_t p, const double* pos, const void* xi_grid, const double* xi_pair,

@@ -636,13 +636,23 @@ int fcm_brownian(fcm_plan_t p, const double* pos, const void* xi_grid, const dou
         e = corr ? launch_gather_both(p, pos, nullptr, nullptr, st)
                  : launch_gather_grid(p, pos, nullptr, nullptr, st);
     int it = 0;
-    // pair part y = C^(1/2) xi_pair into the correction buffer
-    if (e == hipSuccess && corr) e = lanczos_sqrt_pair(p, xi_pair, p->corr, tol, &it, st);
-    // grid part: J~ G^(1/2) xi_grid, with the noise copied into the plan's grid
+    // grid part: J~ G^(1/2) xi_grid, with the noise copied into the plan's
+    // grid, queued on the call's stream first so that it runs while the host
+    // drives the Lanczos steps of the pair part on the side stream
     const size_t nb = (size_t)3 * p->M * p->My * p->Mz * real_size(p->precision);
+    if (e == hipSuccess && corr) {
+        e = hipEventRecord(p->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(p->grid, xi_grid, nb, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = launch_solve(p, p->grid, st, nullptr, false, true);
     if (e == hipSuccess) e = launch_interp(p, p->grid, V, nullptr, st, false, nullptr);
+    // pair part y = C^(1/2) xi_pair into the correction buffer (side stream)
+    if (e == hipSuccess && corr) {
+        e = lanczos_sqrt_pair(p, xi_pair, p->corr, tol, &it, p->side);
+        if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, p->join, 0);
+    }
     // V = sqrt(2 kT / dV) J~ G^(1/2) xi_grid + sqrt(2 kT) y
     const double dV = p->dx * p->dx * p->dx;
     if (e == hipSuccess) {
