@@ -176,8 +176,9 @@ int map_err(hipError_t e) {
 }
 
 // Counting sort into grid bins and pair cells.  The counts are all zero
-// between calls (the scan clears them); after an allocation or a failed launch
-// they are cleared here first.
+// between calls (the scan clears them, and the segment sorts clear the work
+// lists they keep there); after an allocation or a failed launch they are
+// cleared here first.
 hipError_t sort_particles(fcm_plan_impl* P, const double* pos, hipStream_t st) {
     hipError_t e;
     P->repeat_ok = 0;
@@ -187,8 +188,9 @@ hipError_t sort_particles(fcm_plan_impl* P, const double* pos, hipStream_t st) {
     P->counts_dirty = 1;
     if ((e = launch_hash(P, pos, st)) != hipSuccess) return e;
     if ((e = launch_scan(P, st)) != hipSuccess) return e;
+    if ((e = launch_scatter(P, st)) != hipSuccess) return e;
     P->counts_dirty = 0;
-    return launch_scatter(P, st);
+    return hipSuccess;
 }
 
 bool needs_correction(const fcm_plan_impl* P) {
