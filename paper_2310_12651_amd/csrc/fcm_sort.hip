@@ -148,7 +148,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan2_reduce(const int* __rest
     __shared__ int sh[kScanThreads / 64];
     int n, base, first;
     scan2_tile(blockIdx.x, nA, nB, tA, &n, &base, &first);
-    const int* in = blockIdx.x < tA ? counts : counts + nA;
+    const int b = (int)blockIdx.x;
+    const int* in = b < tA ? counts : counts + nA;
     const int i0 = base + threadIdx.x * kScanPerThread;
     int v = 0;
 #pragma unroll
@@ -168,9 +169,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan2_down(int* __restrict__ c
     __shared__ int sh[kScanThreads / 64];
     int n, base, first;
     scan2_tile(blockIdx.x, nA, nB, tA, &n, &base, &first);
-    int* in = blockIdx.x < tA ? counts : counts + nA;
-    int* out = blockIdx.x < tA ? outA : outB;
-    const int last = blockIdx.x < tA ? tA - 1 : tA + tB - 1;
+    const int b = (int)blockIdx.x;
+    int* in = b < tA ? counts : counts + nA;
+    int* out = b < tA ? outA : outB;
+    const int last = b < tA ? tA - 1 : tA + tB - 1;
     // sum of the tiles before this one in its array
     __shared__ int tile_pre;
     int pre = 0;
