@@ -84,6 +84,20 @@ def _case(name):
         w = dict(N=N, L=L, a=A, eta=1.0, grid=72, Sigma=1.4 * L / 72, M_G=15, R_c=4.0,
                  Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
         return w, None
+    if name == "single64":
+        # one particle on a tiled 64^3 grid with M_G = 16: the packed
+        # interpolation with one live slot and the fused x-y FFT passes
+        w = dict(N=1, L=32.0, a=A, eta=1.0, grid=64, Sigma=0.75, M_G=16, R_c=4.2,
+                 Y=np.array([[31.9, 0.3, 17.02]]), F=np.array([[0.4, 1.0, -0.7]]),
+                 T=np.array([[-0.2, 0.5, 0.9]]))
+        return w, None
+    if name == "support14":
+        # M_G = 14 on a tiled 96^3 grid (fused x-y passes with three-quad rows)
+        L, N = 48.0, 33
+        Y = workloads.rsa_positions(N, L, A, rng)
+        w = dict(N=N, L=L, a=A, eta=1.0, grid=96, Sigma=1.4 * L / 96, M_G=14, R_c=3.9,
+                 Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+        return w, None
     if name == "single":
         w = dict(N=1, L=16.0, a=A, eta=1.0, grid=24, Sigma=2 * SIG, M_G=12, R_c=7.5,
                  Y=np.array([[15.9, 0.01, 8.0]]), F=np.array([[1.0, -2.0, 0.5]]),
@@ -93,7 +107,7 @@ def _case(name):
 
 
 CASES = ["small", "ragged54", "wideTorque36", "standard48", "crowded", "tiny16", "support16",
-         "support15", "single"]
+         "support15", "support14", "single64", "single"]
 PREC = {"fp64": (0, 1e-10), "fp32": (1, 1e-5)}
 
 
