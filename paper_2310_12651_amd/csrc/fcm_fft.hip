@@ -999,7 +999,8 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
 }
 
 // The sizes with register passes: M -> (x: M/2 = XN1 XN2), (y, z: M = YN1 YN2 over
-// YW columns), whether the z pass fits in registers.
+// YW columns), whether the z pass runs in registers (at 324 it fits only at one
+// wavefront per SIMD, and the LDS pass is faster).
 #define FCM_REG_SIZES(X)                   \
     X(64, 8, 4, 8, 8, 32, true)            \
     X(72, 18, 2, 12, 6, 36, true)          \
@@ -1012,7 +1013,7 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     X(216, 18, 6, 36, 6, 18, false)        \
     X(256, 16, 8, 16, 16, 16, true)        \
     X(288, 12, 12, 24, 12, 16, true)       \
-    X(324, 18, 9, 18, 18, 9, true)         \
+    X(324, 18, 9, 18, 18, 9, false)        \
     X(384, 24, 8, 48, 8, 16, false)        \
     X(432, 36, 6, 36, 12, 12, false)
 
