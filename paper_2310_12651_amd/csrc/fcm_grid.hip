@@ -138,6 +138,123 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
         b.w = wraps ? bin_start[row + btx + 1] : 0;
         if (rr < 64) runs[rr] = b;
     }
+    // Contributors are staged until the next chunk of candidates would
+    // overflow the stage, so short runs (a few bins of one row) share one
+    // round of z factors and barriers; the summation order is that of the
+    // runs, rows and lanes regardless of where a round ends.
+    int cnt = 0;
+    auto process = [&]() {
+        __syncthreads();
+        // their z factors, one table entry per lane
+        for (int e = lane; e < cnt * MG; e += 64) {
+            const int s = (e * a.mgmul) >> 16, t = e - s * MG;
+            const R d = ((R)t - stg.f[2][s]) * dx;
+            const R d2 = d * d;
+            ZTab<R> z;
+            z.g = fexp2(-d2 * a.e2);
+            z.gd2 = z.g * d2;
+            z.gD = SAMEW ? z.g : fexp2(-d2 * a.e2D);
+            z.gDd = z.gD * d;
+            zt[e] = z;
+        }
+        __syncthreads();
+        for (int q = 0; q < cnt; ++q) {
+            const int sx = __builtin_amdgcn_readfirstlane(stg.s[0][q]);
+            const int sy = __builtin_amdgcn_readfirstlane(stg.s[1][q]);
+            const int sz = __builtin_amdgcn_readfirstlane(stg.s[2][q]);
+            int dxi = gxp - sx;
+            if (dxi < 0) dxi += Mx;
+            int dyi = gyp - sy;
+            if (dyi < 0) dyi += My;
+            const bool in = lact && dxi < MG && dyi < MG;
+            const R dxv = ((R)dxi - stg.f[0][q]) * dx;
+            const R dyv = ((R)dyi - stg.f[1][q]) * dx;
+            const R x2 = dxv * dxv, y2 = dyv * dyv;
+            const R gxy = in ? fexp2(-(x2 + y2) * a.e2) : (R)0;
+            // Column coefficients: with g_z, d_z the z factors, the
+            // contribution to component c at height z is
+            //   g_z (P_c + d_z^2 Q_c) + gD_z (Pt_c + d_z S_c)
+            // where P, Q carry the force kernel g_xy (A + B r_xy^2 +
+            // B d_z^2) F_c and Pt, S the torque kernel's T x d split
+            // into its d_z-free part and its d_z coefficient.
+            const R wf = gxy * (a.A + a.B * (x2 + y2));
+            const R wq = gxy * a.B;
+            R P[3], Q[3], Pt[3] = {0, 0, 0}, S0 = 0, S1 = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                P[c] = wf * stg.F[c][q];
+                Q[c] = wq * stg.F[c][q];
+            }
+            if (TORQUE) {
+                const R gxyD = SAMEW ? gxy : (in ? fexp2(-(x2 + y2) * a.e2D) : (R)0);
+                const R T0 = stg.T[0][q], T1 = stg.T[1][q], T2 = stg.T[2][q];
+                // T x d = (T1 dz - T2 dy, T2 dx - T0 dz, T0 dy - T1 dx)
+                Pt[0] = -gxyD * T2 * dyv;
+                Pt[1] = gxyD * T2 * dxv;
+                Pt[2] = gxyD * (T0 * dyv - T1 * dxv);
+                S0 = gxyD * T1;
+                S1 = -gxyD * T0;
+                if (SAMEW) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) P[c] += Pt[c];
+                }
+            }
+            // tile heights k with (Z0 + k - sz) mod Mz < MG: one or
+            // two runs, as a bit mask
+            int dz0 = Z0 - sz;
+            if (dz0 < 0) dz0 += Mz;
+            const int hi1 = min(TZ, MG - dz0);
+            const int lo2 = Mz - dz0;
+            const int hi2 = min(TZ, Mz - dz0 + MG);
+            unsigned kmask = hi1 > 0 ? low_bits(hi1) : 0u;
+            if (lo2 < TZ) kmask |= low_bits(hi2) & ~low_bits(lo2);
+            kmask = __builtin_amdgcn_readfirstlane(kmask);
+            const ZTab<R>* zq = zt + q * MG;
+            auto step = [&](const int k, const ZTab<R>& e) {
+                if (MODE == ACC_PLAIN) {
+                    R v0 = acc[0][k].s, v1 = acc[1][k].s, v2 = acc[2][k].s;
+                    v0 = v0 + e.g * P[0] + e.gd2 * Q[0];
+                    v1 = v1 + e.g * P[1] + e.gd2 * Q[1];
+                    v2 = v2 + e.g * P[2] + e.gd2 * Q[2];
+                    if (TORQUE) {
+                        if (!SAMEW) {
+                            v0 = v0 + e.gD * Pt[0];
+                            v1 = v1 + e.gD * Pt[1];
+                            v2 = v2 + e.gD * Pt[2];
+                        }
+                        v0 = v0 + e.gDd * S0;
+                        v1 = v1 + e.gDd * S1;
+                    }
+                    acc[0][k].s = v0;
+                    acc[1][k].s = v1;
+                    acc[2][k].s = v2;
+                } else {
+                    R v0 = e.g * P[0] + e.gd2 * Q[0];
+                    R v1 = e.g * P[1] + e.gd2 * Q[1];
+                    R v2 = e.g * P[2] + e.gd2 * Q[2];
+                    if (TORQUE) {
+                        if (!SAMEW) {
+                            v0 = v0 + e.gD * Pt[0];
+                            v1 = v1 + e.gD * Pt[1];
+                            v2 = v2 + e.gD * Pt[2];
+                        }
+                        v0 = v0 + e.gDd * S0;
+                        v1 = v1 + e.gDd * S1;
+                    }
+                    acc[0][k].add(v0);
+                    acc[1][k].add(v1);
+                    acc[2][k].add(v2);
+                }
+            };
+            // The plan keeps TZ <= Mz - MG + 1, so the active heights
+            // are one run and the table entry of height k is zb[k].
+            const ZTab<R>* zb = zq + (hi1 > 0 ? dz0 : dz0 - Mz);
+#pragma unroll
+            for (int k = 0; k < TZ; ++k)
+                if (kmask & (1u << k)) step(k, zb[k]);
+        }
+        __syncthreads();
+    };
     __syncthreads();
     for (int rr = 0; rr < nrows; ++rr) {
         {
@@ -165,7 +282,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
             for (int run = 0; run < 2; ++run) {
                 const int beg = run ? beg1 : beg0, end = run ? end1 : end0;
                 for (int base = beg; base < end; base += kChunk) {
-                    // 1. stage the contributors of this chunk
+                    // the contributors among this chunk of candidates
                     const int p = base + lane;
                     bool take = false;
                     GridRec<R> r;
@@ -181,123 +298,18 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                                (d0z < MG || d0z > Mz - TZ);
                     }
                     const unsigned long long mask = __ballot(take);
-                    const int cnt = __popcll(mask);
-                    if (take) stg.put(__popcll(mask & ((1ull << lane) - 1ull)), r);
-                    __syncthreads();
-                    // 2. their z factors, one table entry per lane
-                    for (int e = lane; e < cnt * MG; e += 64) {
-                        const int s = (e * a.mgmul) >> 16, t = e - s * MG;
-                        const R d = ((R)t - stg.f[2][s]) * dx;
-                        const R d2 = d * d;
-                        ZTab<R> z;
-                        z.g = fexp2(-d2 * a.e2);
-                        z.gd2 = z.g * d2;
-                        z.gD = SAMEW ? z.g : fexp2(-d2 * a.e2D);
-                        z.gDd = z.gD * d;
-                        zt[e] = z;
+                    const int n = __popcll(mask);
+                    if (cnt + n > kChunk) {
+                        process();
+                        cnt = 0;
                     }
-                    __syncthreads();
-                    // 3. accumulate
-                    for (int q = 0; q < cnt; ++q) {
-                        const int sx = __builtin_amdgcn_readfirstlane(stg.s[0][q]);
-                        const int sy = __builtin_amdgcn_readfirstlane(stg.s[1][q]);
-                        const int sz = __builtin_amdgcn_readfirstlane(stg.s[2][q]);
-                        int dxi = gxp - sx;
-                        if (dxi < 0) dxi += Mx;
-                        int dyi = gyp - sy;
-                        if (dyi < 0) dyi += My;
-                        const bool in = lact && dxi < MG && dyi < MG;
-                        const R dxv = ((R)dxi - stg.f[0][q]) * dx;
-                        const R dyv = ((R)dyi - stg.f[1][q]) * dx;
-                        const R x2 = dxv * dxv, y2 = dyv * dyv;
-                        const R gxy = in ? fexp2(-(x2 + y2) * a.e2) : (R)0;
-                        // Column coefficients: with g_z, d_z the z factors, the
-                        // contribution to component c at height z is
-                        //   g_z (P_c + d_z^2 Q_c) + gD_z (Pt_c + d_z S_c)
-                        // where P, Q carry the force kernel g_xy (A + B r_xy^2 +
-                        // B d_z^2) F_c and Pt, S the torque kernel's T x d split
-                        // into its d_z-free part and its d_z coefficient.
-                        const R wf = gxy * (a.A + a.B * (x2 + y2));
-                        const R wq = gxy * a.B;
-                        R P[3], Q[3], Pt[3] = {0, 0, 0}, S0 = 0, S1 = 0;
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            P[c] = wf * stg.F[c][q];
-                            Q[c] = wq * stg.F[c][q];
-                        }
-                        if (TORQUE) {
-                            const R gxyD = SAMEW ? gxy : (in ? fexp2(-(x2 + y2) * a.e2D) : (R)0);
-                            const R T0 = stg.T[0][q], T1 = stg.T[1][q], T2 = stg.T[2][q];
-                            // T x d = (T1 dz - T2 dy, T2 dx - T0 dz, T0 dy - T1 dx)
-                            Pt[0] = -gxyD * T2 * dyv;
-                            Pt[1] = gxyD * T2 * dxv;
-                            Pt[2] = gxyD * (T0 * dyv - T1 * dxv);
-                            S0 = gxyD * T1;
-                            S1 = -gxyD * T0;
-                            if (SAMEW) {
-#pragma unroll
-                                for (int c = 0; c < 3; ++c) P[c] += Pt[c];
-                            }
-                        }
-                        // tile heights k with (Z0 + k - sz) mod Mz < MG: one or
-                        // two runs, as a bit mask
-                        int dz0 = Z0 - sz;
-                        if (dz0 < 0) dz0 += Mz;
-                        const int hi1 = min(TZ, MG - dz0);
-                        const int lo2 = Mz - dz0;
-                        const int hi2 = min(TZ, Mz - dz0 + MG);
-                        unsigned kmask = hi1 > 0 ? low_bits(hi1) : 0u;
-                        if (lo2 < TZ) kmask |= low_bits(hi2) & ~low_bits(lo2);
-                        kmask = __builtin_amdgcn_readfirstlane(kmask);
-                        const ZTab<R>* zq = zt + q * MG;
-                        auto step = [&](const int k, const ZTab<R>& e) {
-                            if (MODE == ACC_PLAIN) {
-                                R v0 = acc[0][k].s, v1 = acc[1][k].s, v2 = acc[2][k].s;
-                                v0 = v0 + e.g * P[0] + e.gd2 * Q[0];
-                                v1 = v1 + e.g * P[1] + e.gd2 * Q[1];
-                                v2 = v2 + e.g * P[2] + e.gd2 * Q[2];
-                                if (TORQUE) {
-                                    if (!SAMEW) {
-                                        v0 = v0 + e.gD * Pt[0];
-                                        v1 = v1 + e.gD * Pt[1];
-                                        v2 = v2 + e.gD * Pt[2];
-                                    }
-                                    v0 = v0 + e.gDd * S0;
-                                    v1 = v1 + e.gDd * S1;
-                                }
-                                acc[0][k].s = v0;
-                                acc[1][k].s = v1;
-                                acc[2][k].s = v2;
-                            } else {
-                                R v0 = e.g * P[0] + e.gd2 * Q[0];
-                                R v1 = e.g * P[1] + e.gd2 * Q[1];
-                                R v2 = e.g * P[2] + e.gd2 * Q[2];
-                                if (TORQUE) {
-                                    if (!SAMEW) {
-                                        v0 = v0 + e.gD * Pt[0];
-                                        v1 = v1 + e.gD * Pt[1];
-                                        v2 = v2 + e.gD * Pt[2];
-                                    }
-                                    v0 = v0 + e.gDd * S0;
-                                    v1 = v1 + e.gDd * S1;
-                                }
-                                acc[0][k].add(v0);
-                                acc[1][k].add(v1);
-                                acc[2][k].add(v2);
-                            }
-                        };
-                        // The plan keeps TZ <= Mz - MG + 1, so the active heights
-                        // are one run and the table entry of height k is zb[k].
-                        const ZTab<R>* zb = zq + (hi1 > 0 ? dz0 : dz0 - Mz);
-#pragma unroll
-                        for (int k = 0; k < TZ; ++k)
-                            if (kmask & (1u << k)) step(k, zb[k]);
-                    }
-                    __syncthreads();
+                    if (take) stg.put(cnt + __popcll(mask & ((1ull << lane) - 1ull)), r);
+                    cnt += n;
                 }
             }
         }
     }
+    if (cnt > 0) process();
     if (lact) {
         const size_t M3 = (size_t)Mx * My * Mz;
         const size_t col = a.tiled ? (size_t)((gyp >> 2) * (Mx << 2) + ((gxp >> 3) << 5) + ((gyp & 3) << 3) +
