@@ -83,10 +83,12 @@ int pow2_floor(int v) {
 void choose_tiles(fcm_plan_impl* P) {
     const int M = P->M, My = P->My, Mz = P->Mz, MG = P->MG;
     double best = 1e300;
-    int bx = 2, by = 2;
-    for (int tx = 2; tx <= 64; ++tx) {
+    int bx = 1, by = 1;
+    // tx <= M - MG + 1 and ty <= My - MG + 1: a particle's support covers the
+    // tile's columns in one run along x and along y
+    for (int tx = 1; tx <= 64 && tx <= M - MG + 1; ++tx) {
         if (M % tx) continue;
-        for (int ty = 2; tx * ty <= 64; ++ty) {
+        for (int ty = 1; tx * ty <= 64 && ty <= My - MG + 1; ++ty) {
             if (My % ty) continue;
             // candidate-scan work per grid point of a wavefront tile
             const double score = (double)(tx + MG - 1) * (ty + MG - 1) / (tx * ty) +

@@ -71,25 +71,25 @@ struct Acc<ACC_WIDE, float> {
     __device__ inline float value() const { return (float)s; }
 };
 
-// the n lowest bits set (0 <= n <= 32)
+// the n lowest bits set (0 <= n <= 32, 0 <= n <= 64)
 __device__ inline unsigned low_bits(int n) { return n >= 32 ? 0xffffffffu : (1u << n) - 1u; }
+__device__ inline unsigned long long low_bits64(int n) { return n >= 64 ? ~0ull : (1ull << n) - 1ull; }
 
-// contributors staged for one round of the spread, one array per field
+// contributors staged for one round of the spread, one array per field:
+// lm: the lanes (tile columns) within the support, as a 64-bit lane mask;
+// km: the tile heights within it, as a bit mask; zo: the byte offset of the
+// z-factor entry of the tile's first height; c (x, y): the distance of the
+// contributor's centre to tile column 0 along the axis (negated); fz: its z
+// fraction; F, T: force and torque
 template <typename R>
 struct Stage {
-    int s[3][kChunk];
-    R f[3][kChunk];
+    unsigned lm[2][kChunk];
+    unsigned km[kChunk];
+    int zo[kChunk];
+    R c[2][kChunk];
+    R fz[kChunk];
     R F[3][kChunk];
     R T[3][kChunk];
-    __device__ inline void put(int k, const GridRec<R>& r) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            s[d][k] = r.s[d];
-            f[d][k] = r.f[d];
-            F[d][k] = r.F[d];
-            T[d][k] = r.T[d];
-        }
-    }
 };
 
 template <typename R, int TZ, int MODE, bool TORQUE, bool SAMEW>
@@ -112,6 +112,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
     const bool lact = lj < a.TY;
     const int gxp = X0 + li, gyp = Y0 + (lact ? lj : 0);
     const R dx = a.dx;
+    const R lidx = (R)li * dx, ljdx = (R)lj * dx;
 
     Acc<MODE, R> acc[3][TZ];
 
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
         // their z factors, one table entry per lane
         for (int e = lane; e < cnt * MG; e += 64) {
             const int s = (e * a.mgmul) >> 16, t = e - s * MG;
-            const R d = ((R)t - stg.f[2][s]) * dx;
+            const R d = ((R)t - stg.fz[s]) * dx;
             const R d2 = d * d;
             ZTab<R> z;
             z.g = fexp2(-d2 * a.e2);
@@ -159,26 +160,21 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
         }
         __syncthreads();
         for (int q = 0; q < cnt; ++q) {
-            const int sx = __builtin_amdgcn_readfirstlane(stg.s[0][q]);
-            const int sy = __builtin_amdgcn_readfirstlane(stg.s[1][q]);
-            const int sz = __builtin_amdgcn_readfirstlane(stg.s[2][q]);
-            int dxi = gxp - sx;
-            if (dxi < 0) dxi += Mx;
-            int dyi = gyp - sy;
-            if (dyi < 0) dyi += My;
-            const bool in = lact && dxi < MG && dyi < MG;
-            const R dxv = ((R)dxi - stg.f[0][q]) * dx;
-            const R dyv = ((R)dyi - stg.f[1][q]) * dx;
-            const R x2 = dxv * dxv, y2 = dyv * dyv;
-            const R gxy = in ? fexp2(-(x2 + y2) * a.e2) : (R)0;
+            const unsigned lo = __builtin_amdgcn_readfirstlane(stg.lm[0][q]);
+            const unsigned hi = __builtin_amdgcn_readfirstlane(stg.lm[1][q]);
+            const bool in = __builtin_amdgcn_inverse_ballot_w64(((unsigned long long)hi << 32) | lo);
+            const R dxv = lidx + stg.c[0][q];
+            const R dyv = ljdx + stg.c[1][q];
+            const R r2 = dxv * dxv + dyv * dyv;
+            const R gxy = in ? fexp2(-r2 * a.e2) : (R)0;
             // Column coefficients: with g_z, d_z the z factors, the
             // contribution to component c at height z is
             //   g_z (P_c + d_z^2 Q_c) + gD_z (Pt_c + d_z S_c)
             // where P, Q carry the force kernel g_xy (A + B r_xy^2 +
             // B d_z^2) F_c and Pt, S the torque kernel's T x d split
             // into its d_z-free part and its d_z coefficient.
-            const R wf = gxy * (a.A + a.B * (x2 + y2));
             const R wq = gxy * a.B;
+            const R wf = wq * r2 + gxy * a.A;
             R P[3], Q[3], Pt[3] = {0, 0, 0}, S0 = 0, S1 = 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -186,30 +182,20 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                 Q[c] = wq * stg.F[c][q];
             }
             if (TORQUE) {
-                const R gxyD = SAMEW ? gxy : (in ? fexp2(-(x2 + y2) * a.e2D) : (R)0);
-                const R T0 = stg.T[0][q], T1 = stg.T[1][q], T2 = stg.T[2][q];
+                const R gxyD = SAMEW ? gxy : (in ? fexp2(-r2 * a.e2D) : (R)0);
+                const R g0 = gxyD * stg.T[0][q], g1 = gxyD * stg.T[1][q], g2 = gxyD * stg.T[2][q];
                 // T x d = (T1 dz - T2 dy, T2 dx - T0 dz, T0 dy - T1 dx)
-                Pt[0] = -gxyD * T2 * dyv;
-                Pt[1] = gxyD * T2 * dxv;
-                Pt[2] = gxyD * (T0 * dyv - T1 * dxv);
-                S0 = gxyD * T1;
-                S1 = -gxyD * T0;
+                Pt[0] = -g2 * dyv;
+                Pt[1] = g2 * dxv;
+                Pt[2] = g0 * dyv - g1 * dxv;
+                S0 = g1;
+                S1 = -g0;
                 if (SAMEW) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) P[c] += Pt[c];
                 }
             }
-            // tile heights k with (Z0 + k - sz) mod Mz < MG: one or
-            // two runs, as a bit mask
-            int dz0 = Z0 - sz;
-            if (dz0 < 0) dz0 += Mz;
-            const int hi1 = min(TZ, MG - dz0);
-            const int lo2 = Mz - dz0;
-            const int hi2 = min(TZ, Mz - dz0 + MG);
-            unsigned kmask = hi1 > 0 ? low_bits(hi1) : 0u;
-            if (lo2 < TZ) kmask |= low_bits(hi2) & ~low_bits(lo2);
-            kmask = __builtin_amdgcn_readfirstlane(kmask);
-            const ZTab<R>* zq = zt + q * MG;
+            const unsigned kmask = __builtin_amdgcn_readfirstlane(stg.km[q]);
             auto step = [&](const int k, const ZTab<R>& e) {
                 if (MODE == ACC_PLAIN) {
                     R v0 = acc[0][k].s, v1 = acc[1][k].s, v2 = acc[2][k].s;
@@ -246,9 +232,9 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
                     acc[2][k].add(v2);
                 }
             };
-            // The plan keeps TZ <= Mz - MG + 1, so the active heights
-            // are one run and the table entry of height k is zb[k].
-            const ZTab<R>* zb = zq + (hi1 > 0 ? dz0 : dz0 - Mz);
+            // the table entry of height k is zb[k] (heights outside kmask
+            // are not read)
+            const ZTab<R>* zb = reinterpret_cast<const ZTab<R>*>(reinterpret_cast<const char*>(zt) + stg.zo[q]);
 #pragma unroll
             for (int k = 0; k < TZ; ++k)
                 if (kmask & (1u << k)) step(k, zb[k]);
@@ -256,60 +242,113 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
         __syncthreads();
     };
     __syncthreads();
-    for (int rr = 0; rr < nrows; ++rr) {
-        {
-            int4 b;
-            if (rr < 64) {
-                b = runs[rr];
+    // One pass over the chunks of candidates of every run of every row, with
+    // one place where the stage is processed (when the next chunk would
+    // overflow it, and once at the end).
+    auto row_runs = [&](int rr) {
+        int4 b;
+        if (rr < 64) {
+            b = runs[rr];
+        } else {
+            const int oz = rr / (a.backy + 1), oy = rr - oz * (a.backy + 1);
+            int bz = btz - oz;
+            if (bz < 0) bz += a.nbz;
+            int by = bty - oy;
+            if (by < 0) by += a.nby;
+            const int row = a.nbx * (by + a.nby * bz);
+            const int bx0 = btx - a.backx;
+            const bool wraps = bx0 < 0;
+            b.x = bin_start[row + (wraps ? bx0 + a.nbx : bx0)];
+            b.y = bin_start[row + (wraps ? a.nbx : btx + 1)];
+            b.z = wraps ? bin_start[row] : 0;
+            b.w = wraps ? bin_start[row + btx + 1] : 0;
+        }
+        b.x = __builtin_amdgcn_readfirstlane(b.x);
+        b.y = __builtin_amdgcn_readfirstlane(b.y);
+        b.z = __builtin_amdgcn_readfirstlane(b.z);
+        b.w = __builtin_amdgcn_readfirstlane(b.w);
+        return b;
+    };
+    int rr = 0, second = 0, base = 0, end = 0;
+    int4 rb = make_int4(0, 0, 0, 0);
+    for (;;) {
+        // the next non-empty run: the first of row rr, then its second
+        while (base >= end && rr < nrows) {
+            if (!second) {
+                rb = row_runs(rr);
+                base = rb.x;
+                end = rb.y;
+                second = 1;
             } else {
-                const int oz = rr / (a.backy + 1), oy = rr - oz * (a.backy + 1);
-                int bz = btz - oz;
-                if (bz < 0) bz += a.nbz;
-                int by = bty - oy;
-                if (by < 0) by += a.nby;
-                const int row = a.nbx * (by + a.nby * bz);
-                const int bx0 = btx - a.backx;
-                const bool wraps = bx0 < 0;
-                b.x = bin_start[row + (wraps ? bx0 + a.nbx : bx0)];
-                b.y = bin_start[row + (wraps ? a.nbx : btx + 1)];
-                b.z = wraps ? bin_start[row] : 0;
-                b.w = wraps ? bin_start[row + btx + 1] : 0;
-            }
-            const int beg0 = __builtin_amdgcn_readfirstlane(b.x);
-            const int end0 = __builtin_amdgcn_readfirstlane(b.y);
-            const int beg1 = __builtin_amdgcn_readfirstlane(b.z);
-            const int end1 = __builtin_amdgcn_readfirstlane(b.w);
-            for (int run = 0; run < 2; ++run) {
-                const int beg = run ? beg1 : beg0, end = run ? end1 : end0;
-                for (int base = beg; base < end; base += kChunk) {
-                    // the contributors among this chunk of candidates
-                    const int p = base + lane;
-                    bool take = false;
-                    GridRec<R> r;
-                    if (lane < kChunk && p < end) {
-                        r = rec[p];
-                        int d0x = X0 - r.s[0];
-                        if (d0x < 0) d0x += Mx;
-                        int d0y = Y0 - r.s[1];
-                        if (d0y < 0) d0y += My;
-                        int d0z = Z0 - r.s[2];
-                        if (d0z < 0) d0z += Mz;
-                        take = (d0x < MG || d0x > Mx - a.TX) && (d0y < MG || d0y > My - a.TY) &&
-                               (d0z < MG || d0z > Mz - TZ);
-                    }
-                    const unsigned long long mask = __ballot(take);
-                    const int n = __popcll(mask);
-                    if (cnt + n > kChunk) {
-                        process();
-                        cnt = 0;
-                    }
-                    if (take) stg.put(cnt + __popcll(mask & ((1ull << lane) - 1ull)), r);
-                    cnt += n;
-                }
+                base = rb.z;
+                end = rb.w;
+                second = 0;
+                ++rr;
             }
         }
+        const bool done = base >= end;
+        bool take = false;
+        GridRec<R> r;
+        // the contributors among this chunk of candidates
+        const int p = base + lane;
+        if (!done && lane < kChunk && p < end) {
+            r = rec[p];
+            int d0x = X0 - r.s[0];
+            if (d0x < 0) d0x += Mx;
+            int d0y = Y0 - r.s[1];
+            if (d0y < 0) d0y += My;
+            int d0z = Z0 - r.s[2];
+            if (d0z < 0) d0z += Mz;
+            take = (d0x < MG || d0x > Mx - a.TX) && (d0y < MG || d0y > My - a.TY) &&
+                   (d0z < MG || d0z > Mz - TZ);
+        }
+        const unsigned long long mask = __ballot(take);
+        const int n = __popcll(mask);
+        if (done || cnt + n > kChunk) {
+            process();
+            cnt = 0;
+        }
+        if (done) break;
+        if (take) {
+            // Along x and y the tile's columns within the support form one
+            // run (the plan keeps TX <= M - MG + 1, TY <= My - MG + 1): with
+            // o the support index of the tile's first column (signed), lanes
+            // i in [max(0, -o), min(T, MG - o)).  Along z, heights k with
+            // (Z0 + k - sz) mod Mz < MG form one run too (TZ <= Mz - MG + 1).
+            const int k = cnt + __popcll(mask & ((1ull << lane) - 1ull));
+            int ox = X0 - r.s[0];
+            if (ox < 0) ox += Mx;
+            if (ox > Mx - a.TX) ox -= Mx;
+            int oy = Y0 - r.s[1];
+            if (oy < 0) oy += My;
+            if (oy > My - a.TY) oy -= My;
+            const int xlo = max(0, -ox), xhi = min(a.TX, MG - ox);
+            const int ylo = max(0, -oy), yhi = min(a.TY, MG - oy);
+            const unsigned long long lm = ((low_bits64(xhi) & ~low_bits64(xlo)) * a.rowrep) &
+                                          (low_bits64(a.TX * yhi) & ~low_bits64(a.TX * ylo));
+            int dz0 = Z0 - r.s[2];
+            if (dz0 < 0) dz0 += Mz;
+            const int hi1 = min(TZ, MG - dz0);
+            const int lo2 = Mz - dz0;
+            const int hi2 = min(TZ, Mz - dz0 + MG);
+            unsigned km = hi1 > 0 ? low_bits(hi1) : 0u;
+            if (lo2 < TZ) km |= low_bits(hi2) & ~low_bits(lo2);
+            stg.lm[0][k] = (unsigned)lm;
+            stg.lm[1][k] = (unsigned)(lm >> 32);
+            stg.km[k] = km;
+            stg.zo[k] = (k * MG + (hi1 > 0 ? dz0 : dz0 - Mz)) * (int)sizeof(ZTab<R>);
+            stg.c[0][k] = ((R)ox - r.f[0]) * dx;
+            stg.c[1][k] = ((R)oy - r.f[1]) * dx;
+            stg.fz[k] = r.f[2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                stg.F[d][k] = r.F[d];
+                stg.T[d][k] = r.T[d];
+            }
+        }
+        cnt += n;
+        base += kChunk;
     }
-    if (cnt > 0) process();
     if (lact) {
         const size_t M3 = (size_t)Mx * My * Mz;
         const size_t col = a.tiled ? (size_t)((gyp >> 2) * (Mx << 2) + ((gxp >> 3) << 5) + ((gyp & 3) << 3) +
@@ -803,6 +842,8 @@ GridArgs<R> make_args(const fcm_plan_impl* P) {
     a.N = (int)P->N;
     a.TX = P->TX;
     a.TY = P->TY;
+    a.rowrep = 0;
+    for (int j = 0; j < P->TY; ++j) a.rowrep |= 1ull << (P->TX * j);
     a.TZ = P->TZ;
     a.nbx = P->nbx;
     a.nby = P->nby;

@@ -91,6 +91,7 @@ struct GridArgs {
     int M, My, Mz;                 // grid points along x, y, z
     int MG, N;
     int TX, TY, TZ;                // spread tile (points)
+    unsigned long long rowrep;     // bit TX*j set for each tile row j < TY (lane = x + TX y)
     int nbx, nby, nbz;             // tiles (= bins) per axis
     int backx, backy, backz;       // bins scanned before the tile's own
     int mgmul;                     // 65536 / MG + 1: e / MG = (e * mgmul) >> 16 for e < 1024
