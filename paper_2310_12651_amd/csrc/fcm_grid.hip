@@ -78,9 +78,9 @@ __device__ inline unsigned long long low_bits64(int n) { return n >= 64 ? ~0ull 
 // contributors staged for one round of the spread, one array per field:
 // lm: the lanes (tile columns) within the support, as a 64-bit lane mask;
 // km: the tile heights within it, as a bit mask; zo: the byte offset of the
-// z-factor entry of the tile's first height; c (x, y): the distance of the
-// contributor's centre to tile column 0 along the axis (negated); fz: its z
-// fraction; F, T: force and torque
+// z-factor entry of the tile's first height; c (x, y): the offset of tile
+// column 0 from the contributor's centre along the axis, in grid spacings
+// (column i lies at (i + c) dx); fz: its z fraction; F, T: force and torque
 template <typename R>
 struct Stage {
     unsigned lm[2][kChunk];
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
     const bool lact = lj < a.TY;
     const int gxp = X0 + li, gyp = Y0 + (lact ? lj : 0);
     const R dx = a.dx;
-    const R lidx = (R)li * dx, ljdx = (R)lj * dx;
+    const R lif = (R)li, ljf = (R)lj;
 
     Acc<MODE, R> acc[3][TZ];
 
@@ -163,8 +163,8 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
             const unsigned lo = __builtin_amdgcn_readfirstlane(stg.lm[0][q]);
             const unsigned hi = __builtin_amdgcn_readfirstlane(stg.lm[1][q]);
             const bool in = __builtin_amdgcn_inverse_ballot_w64(((unsigned long long)hi << 32) | lo);
-            const R dxv = lidx + stg.c[0][q];
-            const R dyv = ljdx + stg.c[1][q];
+            const R dxv = (lif + stg.c[0][q]) * dx;
+            const R dyv = (ljf + stg.c[1][q]) * dx;
             const R r2 = dxv * dxv + dyv * dyv;
             const R gxy = in ? fexp2(-r2 * a.e2) : (R)0;
             // Column coefficients: with g_z, d_z the z factors, the
@@ -337,8 +337,8 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
             stg.lm[1][k] = (unsigned)(lm >> 32);
             stg.km[k] = km;
             stg.zo[k] = (k * MG + (hi1 > 0 ? dz0 : dz0 - Mz)) * (int)sizeof(ZTab<R>);
-            stg.c[0][k] = ((R)ox - r.f[0]) * dx;
-            stg.c[1][k] = ((R)oy - r.f[1]) * dx;
+            stg.c[0][k] = (R)ox - r.f[0];
+            stg.c[1][k] = (R)oy - r.f[1];
             stg.fz[k] = r.f[2];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
