@@ -2,8 +2,9 @@
 
 Cases: a box long in x (48 x 18 x 18 points, M_G = 12: the four-lane FP32
 interpolation of the row-major layout), a flat one (48 x 32 x 24, M_G = 16), and a thin one (64 x 64 x
-16, M_G = 16, so spreading tiles are one point high); every operator and the
-whole mobility, FP64 (1e-10 normwise) and FP32 bulk (1e-5).  Also the copy
+16, M_G = 16, so spreading tiles are one point high), and a slab whose y period
+equals the support (48 x 12 x 24, M_G = 12: every support covers all of y and the
+spreading tiles are one row wide); every operator and the whole mobility, FP64 (1e-10 normwise) and FP32 bulk (1e-5).  Also the copy
 identity of the oracle's box pins, on the GPU: copies of a cube along one axis
 keep the cube's velocities.
 """
@@ -26,6 +27,7 @@ BOXES = {
     "long48x18x18": dict(L=(32.0, 12.0, 12.0), M=(48, 18, 18), Sigma=0.75, M_G=12, R_c=5.0, N=30),
     "flat48x32x24": dict(L=(24.0, 16.0, 12.0), M=(48, 32, 24), Sigma=0.75, M_G=16, R_c=5.0, N=40),
     "thin64x64x16": dict(L=(32.0, 32.0, 8.0), M=(64, 64, 16), Sigma=0.7, M_G=16, R_c=3.5, N=40),
+    "slab48x12x24": dict(L=(24.0, 6.0, 12.0), M=(48, 12, 24), Sigma=0.75, M_G=12, R_c=2.9, N=20),
 }
 
 
