@@ -342,7 +342,7 @@ int plan_allocate(fcm_plan_impl* P, int64_t ncap, int cellcap) {
     FCM_ALLOC(P->keys, (size_t)2 * ncap * sizeof(int));
     FCM_ALLOC(P->ranks, (size_t)2 * ncap * sizeof(int));
     FCM_ALLOC(P->perm, (size_t)2 * ncap * sizeof(int));
-    FCM_ALLOC(P->scan_tmp, 2048 * sizeof(int));
+    FCM_ALLOC(P->scan_tmp, kMaxScanTiles * sizeof(int));
     FCM_ALLOC(P->grec, (size_t)ncap * grid_rec_size(P->precision));
     FCM_ALLOC(P->prec, (size_t)ncap * sizeof(PairRec));
     FCM_ALLOC(P->ppos, (size_t)ncap * sizeof(double4));

@@ -14,6 +14,7 @@ constexpr int kMaxRadixStages = 16;
 constexpr int kMaxSupport = 32;      // largest M_G accepted
 constexpr int kMaxGrid = 1024;       // largest grid per axis accepted
 constexpr int kMaxCellsPerAxis = 128;
+constexpr int kMaxScanTiles = 8192;     // block sums of the bin and cell scans (scan_tmp)
 constexpr int kPairCap = 48;         // neighbours recorded per (particle, z layer)
 
 template <typename R>

@@ -18,9 +18,11 @@ namespace fcm {
 namespace {
 
 constexpr int kScanThreads = 256;
-constexpr int kScanPerThread = 16;
-constexpr int kScanTile = kScanThreads * kScanPerThread;   // 4096
-constexpr int kMaxScanTiles = 2048;              // scan_tmp entries
+constexpr int kScanPerThread = 4;
+constexpr int kScanTile = kScanThreads * kScanPerThread;   // 1024
+static_assert((int64_t)kMaxScanTiles * kScanTile >=
+                  (int64_t)kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis + (1 << 20),
+              "scan tiles cover the largest cell grid and a million bins");
 
 struct HashArgs {
     int N, MG;
