@@ -148,7 +148,7 @@ def valu_for(stage, workload):
 def time_path(plan, args, Y, F, T, V, W, torch, candidates):
     """Warm up; a short pass with every stage timed gives the stage breakdown
     and the dominant stage among `candidates`; then exactly args.steps calls are
-    timed with events around that stage only (three per call instead of twelve,
+    timed with events around that stage only (two per call instead of twelve,
     which would add their gaps to the call) and one per-call event for latency."""
     st = torch.cuda.current_stream()
     for _ in range(args.warmup):

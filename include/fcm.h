@@ -200,7 +200,7 @@ int fcm_plan_last_error(fcm_plan_t p);
 /*
  * Per-stage timing with HIP events.  When enabled, every fcm_mobility call records
  * its stage boundaries (up to 1024 calls are kept): enable = 1 times every stage,
- * enable = 2 + s only stage s (three events a call instead of twelve, so the other
+ * enable = 2 + s only stage s (two events a call instead of twelve, so the other
  * stages run without the events' gaps; the untimed stages read 0), enable = 0
  * stops; other values give FCM_EINVAL.  Changing the mode clears the record, so
  * read it first.  fcm_plan_stage_times

@@ -701,7 +701,8 @@ int fcm_plan_stage_times(fcm_plan_t p, double* ms_out, int* ncalls) {
     for (int s = 0; s < FCM_NUM_STAGES; ++s) ms_out[s] = 0.0;
     const int n = p->events ? p->ev_calls : 0;
     if (n > 0) {
-        hipError_t e = hipEventSynchronize(p->events[(size_t)(n - 1) * kEvPerCall + 9]);
+        const size_t last = (size_t)(n - 1) * kEvPerCall + timing_last_event(p);
+        hipError_t e = hipEventSynchronize(p->events[last]);
         if (e != hipSuccess) return map_err(e);
     }
     for (int c = 0; c < n; ++c) {

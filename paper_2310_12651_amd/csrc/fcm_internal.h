@@ -187,13 +187,20 @@ struct fcm_plan_impl {
 // boundaries on the call's stream (stage s runs from event s to s + 1), 9 the
 // end of the call, 10 and 11 the start and end of the pair correction on the
 // side stream (the last stage).  Timing mode 1 records all of them; mode 2 + s
-// only stage s's two and the end, so that a call timed for one kernel carries
-// three events instead of twelve.
+// only stage s's two, so that a call timed for one kernel carries two events
+// instead of twelve.
 inline bool timing_event(const fcm_plan_impl* P, int i) {
-    if (P->timing <= 1 || i == 9) return true;
+    if (P->timing <= 1) return true;
     const int s = P->timing - 2;
     if (s == 8) return i == 10 || i == 11;
     return i == s || i == s + 1;
+}
+
+// The last event a timed call records (the one to wait for before reading).
+inline int timing_last_event(const fcm_plan_impl* P) {
+    if (P->timing <= 1) return 9;
+    const int s = P->timing - 2;
+    return s == 8 ? 11 : s + 1;
 }
 
 // ---- launchers (each enqueues on `st`; return hipError_t of the launch) ----
