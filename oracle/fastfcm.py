@@ -184,14 +184,22 @@ def wavenumbers(p, axis=0):
     return 2.0 * np.pi * np.fft.fftfreq(M, d=1.0 / M) / L
 
 
-def stokes_solve(p, f):
+def stokes_solve(p, f, workers=None):
     """Inverse Stokes operator L^{-1} in Fourier space (Sec. 2.1 step 2,
     App. A): u^ = (I - k k^T / k^2) f^ / (eta k^2), u^(0) = 0.
 
     Input and output have shape (3, Mx, My, Mz).  Along an axis of even
-    length M the modes with index M/2 are zeroed.
+    length M the modes with index M/2 are zeroed.  ``workers``: None uses
+    numpy's FFT (one thread); a number uses scipy's FFT with that many threads
+    (the same transform, for the largest grids).
     """
-    fh = np.fft.fftn(f, axes=(1, 2, 3))
+    if workers is None:
+        fftn, ifftn = np.fft.fftn, np.fft.ifftn
+    else:
+        import scipy.fft as sfft
+        fftn = lambda a, axes: sfft.fftn(a, axes=axes, workers=workers)
+        ifftn = lambda a, axes: sfft.ifftn(a, axes=axes, workers=workers)
+    fh = fftn(f, axes=(1, 2, 3))
     kx = wavenumbers(p, 0)[:, None, None]
     ky = wavenumbers(p, 1)[None, :, None]
     kz = wavenumbers(p, 2)[None, None, :]
@@ -210,7 +218,7 @@ def stokes_solve(p, f):
         uh[:, :, My // 2, :] = 0.0
     if Mz % 2 == 0:
         uh[:, :, :, Mz // 2] = 0.0
-    return np.real(np.fft.ifftn(uh, axes=(1, 2, 3)))
+    return np.real(ifftn(uh, axes=(1, 2, 3)))
 
 
 def interp(p, Y, u, want_omega=True, chunk=2048):

@@ -94,7 +94,14 @@ def test_stokes_solve_equals_direct_fourier_sum(M):
     assert np.allclose(u, _dft_stokes(p, f), rtol=0, atol=1e-13 * np.abs(u).max())
 
 
-def test_spread_moments_fix_normalisation_and_torque_sign():
+def _spread_fns():
+    from oracle import cgrid
+    return {"numpy": ff.spread, "c": cgrid.spread}
+
+
+@pytest.mark.parametrize("impl", ["numpy", "c"])
+def test_spread_moments_fix_normalisation_and_torque_sign(impl):
+    spread = _spread_fns()[impl]
     L, M = 12.0, 32
     Sg = 1.5 * L / M                     # Sigma / dx = 1.5; M_G = 24 cuts at 8 Sigma: e^-32
     p = ff.Params(L=L, M=M, a=A, Sigma=Sg, M_G=24, R_c=0.0)
@@ -103,15 +110,43 @@ def test_spread_moments_fix_normalisation_and_torque_sign():
     g = np.arange(M) * p.dx
     X = np.stack(np.meshgrid(g, g, g, indexing="ij"), 0)
     F = np.array([[0.4, -1.2, 0.9]])
-    f = ff.spread(p, Y, F, None)
+    f = spread(p, Y, F, None)
     assert np.allclose(dV * f.reshape(3, -1).sum(1), F[0], rtol=0, atol=1e-10)
     T = np.array([[-0.7, 0.3, 1.1]])
-    f = ff.spread(p, Y, np.zeros((1, 3)), T)
+    f = spread(p, Y, np.zeros((1, 3)), T)
     d = X - Y[0][:, None, None, None]
     d -= L * np.round(d / L)
     mom = dV * np.cross(d.reshape(3, -1).T, f.reshape(3, -1).T).sum(0)
     assert np.allclose(mom, T[0], rtol=0, atol=1e-10)          # int x cross f = T
     assert abs(dV * f.sum()) < 1e-12                             # no net force
+
+
+@pytest.mark.parametrize("L,M,MG,Sigma_D,torque", [
+    (20.0, 16, 10, None, True),
+    ((30.0, 12.0, 18.0), (40, 16, 24), 9, 0.9, True),    # box, odd support, Sigma_D != Sigma
+    (17.0, 27, 8, None, False),                         # odd grid, no torques
+    (10.0, 12, 12, None, True),                         # support = grid: every axis wraps
+], ids=["cube", "box-oddMG-SigmaD", "odd-grid-noT", "support-equals-grid"])
+def test_c_spread_equals_numpy_spread(L, M, MG, Sigma_D, torque):
+    """The C spreading used for the largest request-stream grids is the same
+    operator as the numpy oracle's (positions up to two boxes outside)."""
+    spread = _spread_fns()
+    p = ff.Params(L=L, M=M, a=A, Sigma=0.8, M_G=MG, R_c=3.0, Sigma_D=Sigma_D)
+    rng = np.random.default_rng(31)
+    Y = rng.uniform(-25.0, 45.0, (40, 3))
+    F = rng.normal(size=(40, 3))
+    T = rng.normal(size=(40, 3)) if torque else None
+    a = spread["numpy"](p, Y, F, T)
+    b = spread["c"](p, Y, F, T)
+    assert np.abs(a - b).max() < 1e-14 * np.abs(a).max()
+
+
+def test_threaded_fft_solve_equals_numpy_solve():
+    p = ff.Params(L=(30.0, 20.0, 25.0), M=(30, 20, 25), a=A, Sigma=1.0, M_G=10, R_c=0.0)
+    f = np.random.default_rng(5).normal(size=(3, 30, 20, 25))
+    a = ff.stokes_solve(p, f)
+    b = ff.stokes_solve(p, f, workers=4)
+    assert np.abs(a - b).max() < 1e-14 * np.abs(a).max()
 
 
 def test_grid_mobility_symmetric_psd_and_fluid_mean_zero():
