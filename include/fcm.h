@@ -192,7 +192,16 @@ int fcm_plan_info(fcm_plan_t p, int64_t* N, int* grid, int* support, int* precis
  * the host arrays may be NULL.  For fcm_plan_info, grid and cells_per_axis are
  * those along x. */
 int fcm_plan_box_info(fcm_plan_t p, double L[3], int grid[3], int cells[3]);
-/* Device bytes a plan with these sizes would allocate (for admission control). */
+/* Device bytes an fcm_plan_box with these arguments allocates, exactly (the
+ * sum of its buffers: field, twiddles, bin and cell counters, sort arrays,
+ * particle records, neighbour lists, corrections; for admission control).
+ * Returns the status fcm_plan_box would return for invalid arguments. */
+int fcm_plan_footprint_box(int64_t N, const double L[3], double a, double sigma_delta,
+                           const int grid[3], double r_cut, const fcm_options* opt, int64_t* bytes);
+/* An upper bound of the device bytes of any plan with N particles on a cubic
+ * grid of `grid` points in this precision, whatever its box, width, support and
+ * cut-off (it counts one grid bin per grid point and the largest number of pair
+ * cells).  FCM_EINVAL if N or grid is out of range. */
 int fcm_plan_footprint(int64_t N, int grid, int precision, int64_t* bytes);
 /* Synchronises the last call's stream and returns FCM_ENONFINITE if that call saw a
  * non-finite position, else FCM_OK; clears the flag. */

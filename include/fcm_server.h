@@ -13,9 +13,18 @@
  * requests with the same grid, support and precision; idle plans are released,
  * least recently used first, when the budget needs room.
  *
- * Ownership: request arrays are caller-owned DEVICE pointers (N x 3 FP64, as
- * in fcm_mobility) that must stay valid, and must not be written by the caller,
- * until the request is done.  Results land in V and Omega in the caller's order.
+ * Admission: requests are taken in arrival order, except that one waiting for
+ * device memory held by running requests may be passed by later requests that
+ * fit, at most 32 times; after that nothing is admitted past it.
+ *
+ * Ownership and ordering: request arrays are caller-owned DEVICE pointers
+ * (N x 3 FP64, as in fcm_mobility) that must stay valid, and must not be
+ * written by the caller, until the request is done.  The request runs on the
+ * server's own streams: inputs written by device work must either be complete
+ * at submit, or be queued on the stream named in `after_stream`, which the
+ * request then waits for.  Results land in V and Omega in the caller's order.
+ * A request with a non-finite position completes with FCM_ENONFINITE (its
+ * outputs are those of the position wrapped to 0, as in fcm_mobility).
  * Every call returns an FCM_* status (fcm.h); no exception crosses the ABI.
  */
 #ifndef FCM_SERVER_H
@@ -47,6 +56,9 @@ typedef struct {
     const double* T;     /* device N x 3 or NULL (zero torques)              */
     double* V;           /* device N x 3, written                            */
     double* Omega;       /* device N x 3, written, or NULL                   */
+    void* after_stream;  /* hipStream_t of the caller, or NULL: the request  */
+                         /* runs after the work queued there before submit   */
+                         /* (e.g. the kernels that wrote pos, F and T)       */
 } fcm_request;
 
 typedef struct {
@@ -75,7 +87,10 @@ int fcm_server_submit(fcm_server_t s, const fcm_request* req, int64_t* ticket);
 int fcm_server_poll(fcm_server_t s, int64_t ticket, int* state);
 /* Block until the request is done; queue_ms = submit -> launch, run_ms =
  * launch -> completion seen by the server (either may be NULL).  Returns the
- * request's status (FCM_ENOMEM if its plan can never fit the budget). */
+ * request's status (FCM_ENOMEM if its plan can never fit the budget,
+ * FCM_ENONFINITE for a non-finite position) and forgets the ticket.  One thread
+ * may wait for a ticket: a second concurrent waiter gets FCM_EINVAL, as does a
+ * ticket already waited for. */
 int fcm_server_wait(fcm_server_t s, int64_t ticket, double* queue_ms, double* run_ms);
 /* Counters since creation. */
 int fcm_server_get_stats(fcm_server_t s, fcm_server_stats* out);

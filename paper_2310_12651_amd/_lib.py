@@ -19,7 +19,7 @@ EXPORTS = [
     "fcm_options_default", "fcm_plan", "fcm_plan_ex", "fcm_plan_box", "fcm_plan_box_info",
     "fcm_plan_destroy", "fcm_mobility",
     "fcm_mobility_repeat", "fcm_brownian", "fcm_brownian_reserve", "fcm_spread", "fcm_solve", "fcm_interp", "fcm_correct", "fcm_plan_info",
-    "fcm_plan_footprint", "fcm_plan_last_error", "fcm_status_string", "fcm_plan_set_timing",
+    "fcm_plan_footprint", "fcm_plan_footprint_box", "fcm_plan_last_error", "fcm_status_string", "fcm_plan_set_timing",
     "fcm_plan_stage_times",
 ]
 STAGES = ["sort", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_solve", "fft_y_inv", "fft_x_inv",
@@ -73,6 +73,8 @@ def library():
         "fcm_plan_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(ci), ctypes.POINTER(ci),
                            ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
         "fcm_plan_footprint": ([i64, ci, ci, ctypes.POINTER(i64)], ci),
+        "fcm_plan_footprint_box": ([i64, ctypes.POINTER(cd), cd, cd, ctypes.POINTER(ci), cd,
+                                    ctypes.POINTER(Options), ctypes.POINTER(i64)], ci),
         "fcm_plan_last_error": ([vp], ci),
         "fcm_status_string": ([ci], ctypes.c_char_p),
         "fcm_plan_set_timing": ([vp, ci], ci),
@@ -133,6 +135,18 @@ def fcm_plan_footprint(N, grid, precision):
     b = ctypes.c_int64()
     _check(library().fcm_plan_footprint(int(N), int(grid), int(precision), ctypes.byref(b)),
            "fcm_plan_footprint")
+    return b.value
+
+
+def fcm_plan_footprint_box(N, L, a, Sigma, grid, r_cut, options=None):
+    """Exact device bytes of the plan fcm_plan_box would build (L, grid: one
+    number for a cube or three)."""
+    L3 = (ctypes.c_double * 3)(*([float(L)] * 3 if isinstance(L, (int, float)) else [float(x) for x in L]))
+    g3 = (ctypes.c_int * 3)(*([int(grid)] * 3 if isinstance(grid, int) else [int(x) for x in grid]))
+    b = ctypes.c_int64()
+    opt = None if options is None else ctypes.byref(options)
+    _check(library().fcm_plan_footprint_box(int(N), L3, float(a), float(Sigma), g3, float(r_cut), opt,
+                                            ctypes.byref(b)), "fcm_plan_footprint_box")
     return b.value
 
 

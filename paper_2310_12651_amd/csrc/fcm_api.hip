@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "fcm_internal.h"
@@ -424,7 +425,10 @@ int64_t plan_bytes(int64_t ncap, const int grid[3], int precision, int cellcap, 
     b += 3 * ncap * (int64_t)(kPairCap + 1) * (int64_t)sizeof(int);
     b += 6 * ncap * (int64_t)sizeof(double);
     b += ncap * (int64_t)(grid_rec_size(precision) + sizeof(PairRec) + sizeof(double4));
-    b += (int64_t)(2 * (nbins + 1) + 2 * (cellcap + 1)) * (int64_t)sizeof(int) + 2048 * 4 + 64;
+    // counts and starts of the bins and cells, the scan's block sums, the
+    // reduction partials and the flags (the buffers of plan_allocate)
+    b += (int64_t)(2 * (nbins + 1) + 2 * (cellcap + 1)) * (int64_t)sizeof(int);
+    b += (int64_t)kMaxScanTiles * (int64_t)sizeof(int) + 1024 * (int64_t)sizeof(double) + 16 * (int64_t)sizeof(int);
     return b;
 }
 
@@ -443,18 +447,26 @@ int fcm_options_default(fcm_options* opt) {
 }
 
 int fcm_plan_footprint(int64_t N, int grid, int precision, int64_t* bytes) {
-    if (!bytes || N <= 0 || grid <= 0) return FCM_EINVAL;
-    const int64_t M = grid;
-    const int64_t rs = (int64_t)real_size(precision);
-    int64_t b = 3 * M * M * M * rs;                     // field / spectrum
-    b += M * 2 * rs;                                    // twiddles
-    b += 6 * N * (int64_t)sizeof(int);                  // keys, ranks, perm
-    b += N * (int64_t)(grid_rec_size(precision) + sizeof(PairRec) + sizeof(double4));
-    const int64_t nbins_max = (M / 2) * (M / 2) * (M / 2);
-    const int64_t cells = (int64_t)kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis;
-    b += 2 * (nbins_max + 1) * (int64_t)sizeof(int) + 2 * (cells + 1) * (int64_t)sizeof(int);
-    b += 4096 * (int64_t)sizeof(int);
-    *bytes = b;
+    // An upper bound over every box, width, support and cut-off: at most one
+    // grid bin per grid point (supports as long as the grid leave tiles of
+    // one point) and kMaxCellsPerAxis^3 pair cells.
+    if (!bytes || N <= 0 || N > (int64_t)1 << 29 || !is_smooth_even(grid)) return FCM_EINVAL;
+    if (precision != FCM_FP64 && precision != FCM_FP32_BULK) return FCM_EINVAL;
+    const int g3[3] = {grid, grid, grid};
+    const int64_t nbins = (int64_t)grid * grid * grid;
+    const int cells = kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis;
+    *bytes = plan_bytes(N, g3, precision, cells, (int)std::min<int64_t>(nbins, 1 << 30));
+    return FCM_OK;
+}
+
+int fcm_plan_footprint_box(int64_t N, const double L[3], double a, double sigma_delta,
+                           const int grid[3], double r_cut, const fcm_options* opt, int64_t* bytes) {
+    if (!bytes) return FCM_EINVAL;
+    fcm_plan_impl d;
+    const int st = plan_derive(&d, N, L, a, sigma_delta, grid, r_cut, opt);
+    if (st != FCM_OK) return st;
+    const int g3[3] = {d.M, d.My, d.Mz};
+    *bytes = plan_bytes(N, g3, d.precision, d.ncells, d.nbins);
     return FCM_OK;
 }
 

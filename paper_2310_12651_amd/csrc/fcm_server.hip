@@ -1,10 +1,13 @@
 // Request server for fast-FCM mobility evaluations (include/fcm_server.h).
 //
-// A worker thread owns the device work: it admits queued requests in arrival
-// order whenever one of its stream slots is free and the plan the request needs
-// fits the device-byte budget, launches the request's evaluation on that
-// slot's stream (each fcm_mobility call is stream-ordered and allocation-free),
-// records a completion event, and retires the slot when the event has fired.
+// A worker thread owns the device work: it admits queued requests whenever one
+// of its stream slots is free and the plan the request needs fits the
+// device-byte budget, launches the request's evaluation on that slot's stream
+// (each fcm_mobility call is stream-ordered and allocation-free), records a
+// completion event, and retires the slot when the event has fired.  Requests
+// are taken in arrival order, but one that has to wait for memory held by
+// running requests is passed by later ones that fit (at most kMaxBypass times;
+// then admission holds for it, so large requests are not starved).
 // Plans are cached and re-bound to later requests with the same grid, support
 // and precision, so grids, twiddles and sort/cell buffers stay resident;
 // idle plans are freed least-recently-used first when room is needed.
@@ -34,17 +37,24 @@ struct CachedPlan {
     uint64_t last_use = 0;
 };
 
+// later requests admitted ahead of one that waits for memory, at most
+constexpr int kMaxBypass = 32;
+
 struct Req {
     fcm_request r;
     int64_t ticket = 0;
     int state = 0;   // 0 queued, 1 running, 2 done
     int status = FCM_OK;
+    int bypassed = 0;            // later requests admitted ahead of this one
+    bool waited = false;         // a thread is in (or has been through) fcm_server_wait
+    hipEvent_t after = nullptr;  // recorded on the caller's stream at submit, or null
     Clock::time_point t_submit, t_launch, t_done;
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    int* nonfinite = nullptr;    // pinned host word: the plan's non-finite flag after the call
     Req* req = nullptr;
     CachedPlan* plan = nullptr;
 };
@@ -61,6 +71,7 @@ struct fcm_server_impl {
     std::unordered_map<int64_t, Req*> reqs;
     std::vector<Slot> slots;
     std::vector<CachedPlan*> cache;
+    std::vector<hipEvent_t> free_events;   // for the caller-stream dependencies
     int64_t next_ticket = 1;
     int64_t budget = 0;
     uint64_t use_clock = 0;
@@ -71,6 +82,7 @@ struct fcm_server_impl {
 
     void run();
     bool retire_locked();
+    void release_event_locked(Req* r);
     bool admit_locked();
     CachedPlan* plan_for_locked(const fcm_plan_impl& d, int* status);
     void evict_one_locked();
@@ -187,7 +199,11 @@ bool fcm_server_impl::retire_locked() {
         if (q == hipErrorNotReady) continue;
         Req* r = s.req;
         r->t_done = Clock::now();
-        if (q != hipSuccess) r->status = FCM_EDEVICE;
+        if (q != hipSuccess)
+            r->status = FCM_EDEVICE;
+        else if (*s.nonfinite)
+            r->status = FCM_ENONFINITE;   // a position was NaN or infinite
+        release_event_locked(r);
         r->state = 2;
         if (r->status == FCM_OK)
             stats.completed++;
@@ -204,10 +220,20 @@ bool fcm_server_impl::retire_locked() {
     return any;
 }
 
-// launch queued requests (in arrival order) while slots and memory allow
+void fcm_server_impl::release_event_locked(Req* r) {
+    if (r->after) {
+        free_events.push_back(r->after);
+        r->after = nullptr;
+    }
+}
+
+// launch queued requests while slots and memory allow: in arrival order, past
+// the ones that wait for memory held by running requests (each may be passed
+// kMaxBypass times)
 bool fcm_server_impl::admit_locked() {
     bool any = false;
-    while (!queue.empty()) {
+    size_t i = 0;
+    while (i < queue.size()) {
         Slot* free_slot = nullptr;
         for (Slot& s : slots)
             if (!s.req) {
@@ -215,17 +241,23 @@ bool fcm_server_impl::admit_locked() {
                 break;
             }
         if (!free_slot) break;
-        Req* r = queue.front();
+        Req* r = queue[i];
         fcm_plan_impl d;
         int st = derive_request(opt, r->r, &d);
         CachedPlan* c = nullptr;
         if (st == FCM_OK) c = plan_for_locked(d, &st);
-        if (!c && st == FCM_OK) break;   // needs room held by running requests
-        queue.pop_front();
+        if (!c && st == FCM_OK) {        // needs room held by running requests
+            if (r->bypassed >= kMaxBypass) break;   // admit nothing past it
+            ++i;
+            continue;
+        }
+        for (size_t j = 0; j < i; ++j) queue[j]->bypassed++;
+        queue.erase(queue.begin() + (std::ptrdiff_t)i);
         if (!c) {
             r->status = st;
             r->state = 2;
             r->t_launch = r->t_done = Clock::now();
+            release_event_locked(r);
             stats.failed++;
             done_cv.notify_all();
             any = true;
@@ -234,13 +266,25 @@ bool fcm_server_impl::admit_locked() {
         c->busy = true;
         r->state = 1;
         r->t_launch = Clock::now();
-        st = fcm_mobility(c->P, r->r.pos, r->r.F, r->r.T, r->r.V, r->r.Omega, free_slot->stream);
-        if (st == FCM_OK && hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess) st = FCM_EDEVICE;
+        *free_slot->nonfinite = 0;
+        hipStream_t ss = free_slot->stream;
+        st = FCM_OK;
+        if (r->after && hipStreamWaitEvent(ss, r->after, 0) != hipSuccess) st = FCM_EDEVICE;
+        if (st == FCM_OK) st = fcm_mobility(c->P, r->r.pos, r->r.F, r->r.T, r->r.V, r->r.Omega, ss);
+        // the plan's non-finite flag (raised by the hash of this call) to the
+        // slot's host word, then cleared for the plan's next request
+        if (st == FCM_OK &&
+            (hipMemcpyAsync(free_slot->nonfinite, c->P->flag, sizeof(int), hipMemcpyDeviceToHost, ss) !=
+                 hipSuccess ||
+             fcm::launch_fill(c->P->flag, 1, 0, ss) != hipSuccess))
+            st = FCM_EDEVICE;
+        if (st == FCM_OK && hipEventRecord(free_slot->done, ss) != hipSuccess) st = FCM_EDEVICE;
         if (st != FCM_OK) {
             c->busy = false;
             r->status = st;
             r->state = 2;
             r->t_done = Clock::now();
+            release_event_locked(r);
             stats.failed++;
             done_cv.notify_all();
         } else {
@@ -310,14 +354,17 @@ int fcm_server_create(fcm_server_t* out, const fcm_server_options* opt_in) {
     s->slots.resize(o.slots);
     for (Slot& sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&sl.nonfinite, sizeof(int), hipHostMallocDefault) != hipSuccess) {
             for (Slot& x : s->slots) {
                 if (x.stream) (void)hipStreamDestroy(x.stream);
                 if (x.done) (void)hipEventDestroy(x.done);
+                if (x.nonfinite) (void)hipHostFree(x.nonfinite);
             }
             delete s;
             return FCM_EDEVICE;
         }
+        *sl.nonfinite = 0;
     }
     s->worker = std::thread([s] { s->run(); });
     *out = s;
@@ -342,6 +389,23 @@ int fcm_server_submit(fcm_server_t s, const fcm_request* req, int64_t* ticket) {
         if ((int)s->queue.size() >= s->opt.max_queue) {
             delete r;
             return FCM_EBUSY;
+        }
+        if (req->after_stream) {
+            // the request runs after the work the caller's stream holds now
+            hipEvent_t ev = nullptr;
+            if (!s->free_events.empty()) {
+                ev = s->free_events.back();
+                s->free_events.pop_back();
+            } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                delete r;
+                return FCM_EDEVICE;
+            }
+            if (hipEventRecord(ev, (hipStream_t)req->after_stream) != hipSuccess) {
+                s->free_events.push_back(ev);
+                delete r;
+                return FCM_EDEVICE;
+            }
+            r->after = ev;
         }
         r->ticket = s->next_ticket++;
         s->reqs[r->ticket] = r;
@@ -368,6 +432,8 @@ int fcm_server_wait(fcm_server_t s, int64_t ticket, double* queue_ms, double* ru
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return FCM_EINVAL;
     Req* r = it->second;
+    if (r->waited) return FCM_EINVAL;   // another thread waits for this ticket
+    r->waited = true;
     s->work_cv.notify_one();
     s->done_cv.wait(lk, [&] { return r->state == 2; });
     if (queue_ms) *queue_ms = ms_between(r->t_submit, r->t_launch);
@@ -397,12 +463,17 @@ int fcm_server_destroy(fcm_server_t s) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.nonfinite) (void)hipHostFree(sl.nonfinite);
     }
+    for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
     for (CachedPlan* c : s->cache) {
         fcm::plan_free(c->P);
         delete c;
     }
-    for (auto& kv : s->reqs) delete kv.second;
+    for (auto& kv : s->reqs) {
+        if (kv.second->after) (void)hipEventDestroy(kv.second->after);
+        delete kv.second;
+    }
     delete s;
     return FCM_OK;
 }

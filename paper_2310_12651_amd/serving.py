@@ -18,7 +18,7 @@ class Request(ctypes.Structure):
                 ("sigma_delta", ctypes.c_double), ("grid", ctypes.c_int), ("r_cut", ctypes.c_double),
                 ("support", ctypes.c_int), ("eta", ctypes.c_double),
                 ("pos", ctypes.c_void_p), ("F", ctypes.c_void_p), ("T", ctypes.c_void_p),
-                ("V", ctypes.c_void_p), ("Omega", ctypes.c_void_p)]
+                ("V", ctypes.c_void_p), ("Omega", ctypes.c_void_p), ("after_stream", ctypes.c_void_p)]
 
 
 class ServerOptions(ctypes.Structure):
@@ -78,11 +78,18 @@ class Server:
         _check(lib.fcm_server_create(ctypes.byref(h), ctypes.byref(o)), "fcm_server_create")
         self._h = h
 
-    def submit(self, N, L, a, Sigma, grid, r_cut, pos, F, T=None, V=None, Omega=None, support=0, eta=1.0):
+    def submit(self, N, L, a, Sigma, grid, r_cut, pos, F, T=None, V=None, Omega=None, support=0, eta=1.0,
+               stream=None):
+        """Queue one evaluation; it runs after the work queued so far on
+        ``stream`` (default: the current stream, where torch wrote the inputs)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
         r = Request(N=int(N), L=float(L), a=float(a), sigma_delta=float(Sigma), grid=int(grid),
                     r_cut=float(r_cut), support=int(support), eta=float(eta),
                     pos=pos.data_ptr(), F=F.data_ptr(), T=None if T is None else T.data_ptr(),
-                    V=V.data_ptr(), Omega=None if Omega is None else Omega.data_ptr())
+                    V=V.data_ptr(), Omega=None if Omega is None else Omega.data_ptr(),
+                    after_stream=stream.cuda_stream)
         t = ctypes.c_int64()
         st = _lib().fcm_server_submit(self._h, ctypes.byref(r), ctypes.byref(t))
         _check(st, "fcm_server_submit")

@@ -93,6 +93,29 @@ def test_footprint_scales_with_grid_and_precision(lib):
     assert fcm.fcm_plan_footprint(1000, 64, 1) < f32
 
 
+@pytest.mark.parametrize("N,L,Sigma,grid,rc,prec", [
+    (100_000, 161.2, 0.63, 256, 3.46, 1),
+    (100_000, 161.2, 0.63, 256, 3.46, 0),
+    (64, 40.0, 1.13, 32, 10.8, 0),
+    (2000, (48.0, 18.0, 18.0), 1.0, (48, 18, 18), 4.0, 1),
+])
+def test_footprint_box_is_exact_size_and_below_the_bound(lib, N, L, Sigma, grid, rc, prec):
+    """The exact footprint counts at least the field and the per-particle
+    state, and the grid-only bound covers it."""
+    o = fcm.fcm_options_default()
+    o.precision = prec
+    ex = _lib.fcm_plan_footprint_box(N, L, 1.0, Sigma, grid, rc, o)
+    g = grid if isinstance(grid, int) else grid[0]
+    g3 = (grid,) * 3 if isinstance(grid, int) else grid
+    rs = 8 if prec == 0 else 4
+    field = 3 * g3[0] * g3[1] * g3[2] * rs
+    assert ex > field + N * (24 + 3 * 49 * 4 + 6 * 8)
+    if isinstance(grid, int):
+        assert ex <= fcm.fcm_plan_footprint(N, g, prec)
+    with pytest.raises(fcm.FCMError):
+        _lib.fcm_plan_footprint_box(N, L, 1.0, 0.1, grid, rc, o)      # Sigma below sigma
+
+
 def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(_lib, "_lib", None)

@@ -189,9 +189,10 @@ def test_mobility_matches_oracle(case, prec):
 def test_optional_torque_and_omega(case, prec):
     """T = NULL means zero torques; Omega = NULL skips angular velocities.
 
-    With forces alone Omega can nearly cancel (one particle: zero by symmetry
-    up to the grid's discretisation), so its error is measured against the
-    larger of |Omega| and the angular scale |V| / a of the same forces."""
+    FP64 meets the plain normwise bar on Omega.  In FP32 Omega from forces
+    alone can nearly cancel (one particle: zero by symmetry up to the grid's
+    discretisation), so its FP32 error is measured against the larger of |Omega|
+    and the angular scale |V| / a of the same forces."""
     w = case["w"]
     p = case["p"]
     tol = PREC[prec][1]
@@ -199,8 +200,11 @@ def test_optional_torque_and_omega(case, prec):
     V, W = plan.mobility(dev(w["Y"]), dev(w["F"]), None)
     Vr, Wr = ff.mobility(p, w["Y"], w["F"], None)
     assert normwise(host(V), Vr) < tol
-    scale = max(np.linalg.norm(Wr), np.linalg.norm(Vr) / w["a"])
-    assert np.linalg.norm(host(W) - Wr) < tol * scale
+    if prec == "fp64":
+        assert normwise(host(W), Wr) < 1e-10
+    else:
+        scale = max(np.linalg.norm(Wr), np.linalg.norm(Vr) / w["a"])
+        assert np.linalg.norm(host(W) - Wr) < tol * scale
     V2, W2 = plan.mobility(dev(w["Y"]), dev(w["F"]), dev(w["T"]), want_omega=False)
     assert W2 is None and normwise(host(V2), case["V"]) < tol
 
