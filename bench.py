@@ -218,8 +218,9 @@ def cpu_baseline(w, n_sample, V_gpu, W_gpu):
 
 def serving_leg(args, torch):
     """The mixed-size request stream: the one-request-at-a-time FP64 path
-    (closed loop, then Poisson arrivals at 0.8x its throughput) against the
-    continuous-batching FP32-bulk server (8 slots) on the same arrivals."""
+    (closed loop, then Poisson arrivals at 0.8x and at 1.5x its throughput)
+    against the continuous-batching FP32-bulk server (8 slots) on the same
+    arrivals."""
     import numpy as np
 
     import workloads
@@ -253,6 +254,11 @@ def serving_leg(args, torch):
     rng = np.random.default_rng(workloads.SEED_BASE + 5)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
     lat64, mk64 = replay(s64, reqs, tensors, arrivals)
+    # and at 1.5x the FP64 path's closed-loop rate, beyond what it can serve
+    rate_hi = 1.5 * len(reqs) / T_seq
+    arrivals_hi = np.cumsum(np.random.default_rng(workloads.SEED_BASE + 6).exponential(1.0 / rate_hi,
+                                                                                       size=len(reqs)))
+    lat64h, mk64h = replay(s64, reqs, tensors, arrivals_hi)
     st64 = s64.stats()
     s64.close()
     log(f"[bench] fp64 one-at-a-time: closed loop {T_seq:.2f} s; Poisson at {rate:.1f}/s: p50 "
@@ -260,11 +266,14 @@ def serving_leg(args, torch):
     s32 = Server(slots=8, precision=FCM_FP32_BULK, max_bytes=budget)
     warm(s32)
     lat32, mk32 = replay(s32, reqs, tensors, arrivals)
+    lat32h, mk32h = replay(s32, reqs, tensors, arrivals_hi)
     _, T32 = replay(s32, reqs, tensors, None)
     st32 = s32.stats()
     s32.close()
     log(f"[bench] fp32 server: p50 {pct(lat32, 50):.2f} ms p99 {pct(lat32, 99):.2f} ms makespan "
         f"{mk32:.2f} s; closed loop {T32:.2f} s")
+    log(f"[bench] at {rate_hi:.1f}/s: fp64 p50 {pct(lat64h, 50):.2f} p99 {pct(lat64h, 99):.2f} ms makespan "
+        f"{mk64h:.2f} s; fp32 server p50 {pct(lat32h, 50):.2f} p99 {pct(lat32h, 99):.2f} ms makespan {mk32h:.2f} s")
     return {
         "requests": len(reqs), "particles": total, "arrival_rate_per_s": rate,
         "fp64_one_at_a_time": {"p50_ms": pct(lat64, 50), "p99_ms": pct(lat64, 99),
@@ -277,6 +286,12 @@ def serving_leg(args, torch):
                                 "inflight_peak": st32["inflight_peak"], "plans_built": st32["plans_built"],
                                 "plans_rebound": st32["plans_rebound"],
                                 "plans_evicted": st32["plans_evicted"]},
+        "above_fp64_saturation": {
+            "arrival_rate_per_s": rate_hi,
+            "fp64_one_at_a_time": {"p50_ms": pct(lat64h, 50), "p99_ms": pct(lat64h, 99),
+                                   "throughput_evals_per_s": total / mk64h},
+            "fp32_server_8_slots": {"p50_ms": pct(lat32h, 50), "p99_ms": pct(lat32h, 99),
+                                    "throughput_evals_per_s": total / mk32h}},
     }
 
 
@@ -620,8 +635,8 @@ def main():
     N = w["N"]
     V = torch.empty((N, 3), dtype=torch.float64, device="cuda")
     W = torch.empty_like(V)
-    mk = lambda prec: Plan(N, w["L"], w["a"], w["Sigma"], w["grid"], w["R_c"], support=w["M_G"],
-                           precision=prec)
+    mk = lambda prec, kahan=0: Plan(N, w["L"], w["a"], w["Sigma"], w["grid"], w["R_c"], support=w["M_G"],
+                                    precision=prec, kahan=kahan)
     if args.copy_calib:
         src = torch.ones(3 * w["grid"] ** 3, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -646,16 +661,24 @@ def main():
     log(f"[bench] fp32 repeat at the same positions {repeat_ms:.3f} ms/step")
     log(f"[bench] fp32 {r32['ms_per_step']:.3f} ms/step  stages {r32['stages_ms']}")
     V32, W32 = V.cpu().numpy(), W.cpu().numpy()
+    plan32.close()
+    # the same FP32 path with Kahan-compensated sums in the spreading tiles
+    plan_k = mk(FCM_FP32_BULK, kahan=1)
+    rk = time_path(plan_k, args, Y, F, T, V, W, torch, grid_stages)
+    plan_k.close()
+    Vk, Wk = V.cpu().numpy(), W.cpu().numpy()
+    log(f"[bench] fp32 kahan {rk['ms_per_step']:.3f} ms/step  spread {rk['stages_ms']['spread']:.4f} ms")
     r64 = None
     acc64 = None
     if not args.no_fp64:
-        plan32.close()
         plan64 = mk(FCM_FP64)
         r64 = time_path(plan64, args, Y, F, T, V, W, torch, grid_stages)
         log(f"[bench] fp64 {r64['ms_per_step']:.3f} ms/step  stages {r64['stages_ms']}")
         V64, W64 = V.cpu().numpy(), W.cpu().numpy()
         acc64 = dict(relV_fp32_vs_fp64=float(np.linalg.norm(V32 - V64) / np.linalg.norm(V64)),
-                     relW_fp32_vs_fp64=float(np.linalg.norm(W32 - W64) / np.linalg.norm(W64)))
+                     relW_fp32_vs_fp64=float(np.linalg.norm(W32 - W64) / np.linalg.norm(W64)),
+                     relV_fp32_kahan_vs_fp64=float(np.linalg.norm(Vk - V64) / np.linalg.norm(V64)),
+                     relW_fp32_kahan_vs_fp64=float(np.linalg.norm(Wk - W64) / np.linalg.norm(W64)))
         plan64.close()
     stages = {k: v for k, v in r32["stages_ms"].items()}
     roof = None
@@ -702,6 +725,9 @@ def main():
                    "M_G": w["M_G"], "R_c": w["R_c"], "L": w["L"], "parallelism": "single GPU"},
         "latency_ms": {"p50": r32["p50_ms"], "p99": r32["p99_ms"]},
         "repeat_same_positions": {"ms_per_step": repeat_ms, "value": N / (repeat_ms * 1e-3)},
+        "fp32_kahan_spread": {"value": N / (rk["ms_per_step"] * 1e-3), "ms_per_step": rk["ms_per_step"],
+                              "spread_ms": round(rk["stages_ms"]["spread"], 5),
+                              "spread_ms_plain": round(stages["spread"], 5)},
         "stages_ms": {k: round(v, 5) for k, v in stages.items()},
         "stage_gbs": per_stage_gbs,
         "fp64": None if r64 is None else {"value": N / (r64["ms_per_step"] * 1e-3),

@@ -106,8 +106,13 @@ int fcm_plan_ex(fcm_plan_t* out, int64_t N, double L, double a, double sigma_del
  * the Fourier wave numbers are 2 pi j / L[d] per axis (Sec. 2.1) and the pair
  * cells m_d = max(int(L[d]/R_c), 3) per axis (Sec. 4).  Grid buffers of the
  * stage calls hold 3 x grid[2] x grid[1] x grid[0] values (x fastest).
- * Errors: as fcm_plan_ex; FCM_EINVAL also for unequal spacings or a support
- * larger than the shortest grid axis; FCM_ERANGE if r_cut >= min(L)/2.
+ * The support M_G may be longer than the z axis when grid[2] is 8, 12 or 16 (the
+ * paper's rod runs use 512 x 512 x 8 points, Sec. 6.3): a particle's support
+ * then wraps onto itself along z and its coinciding points add, as the
+ * periodic sums of Sec. 2.1 read on such a grid.
+ * Errors: as fcm_plan_ex; FCM_EINVAL also for unequal spacings, a support
+ * longer than the x or y axis, or longer than a z axis other than 8, 12 or 16
+ * points; FCM_ERANGE if r_cut >= min(L)/2.
  */
 int fcm_plan_box(fcm_plan_t* out, int64_t N, const double L[3], double a, double sigma_delta,
                  const int grid[3], double r_cut, const fcm_options* opt);

@@ -112,6 +112,9 @@ void choose_tiles(fcm_plan_impl* P) {
             P->TZ = t;
             break;
         }
+    // a support longer than the z axis: one tile spans the axis (Mz is one of
+    // the tile heights, checked by plan_derive) and every height is covered
+    if (MG > Mz) P->TZ = Mz;
     // One wavefront spreads a tile: with fewer than 8 tiles per SIMD (8192 on
     // the 1024 SIMDs) latency and crowded tiles are poorly hidden, and tiles
     // of height 8 pay less than their extra candidate scans (measured: 192^3
@@ -238,8 +241,6 @@ int plan_derive(fcm_plan_impl* P, int64_t N, const double L[3], double a, double
     if (!(r_cut >= 0.0) || !isfinite(r_cut)) return FCM_EINVAL;
     const double Lmin = fmin(L[0], fmin(L[1], L[2]));
     if (r_cut >= 0.5 * Lmin) return FCM_ERANGE;
-    const int gmin = grid[0] < grid[1] ? (grid[0] < grid[2] ? grid[0] : grid[2])
-                                       : (grid[1] < grid[2] ? grid[1] : grid[2]);
     const int gmax = grid[0] > grid[1] ? (grid[0] > grid[2] ? grid[0] : grid[2])
                                        : (grid[1] > grid[2] ? grid[1] : grid[2]);
     int MG = opt.support;
@@ -249,7 +250,13 @@ int plan_derive(fcm_plan_impl* P, int64_t N, const double L[3], double a, double
         if (MG & 1) ++MG;
         if (MG < 8) MG = 8;
     }
-    if (MG < 2 || MG > kMaxSupport || MG > gmin) return FCM_EINVAL;
+    // Along x and y the support fits the axis.  Along z it may be longer (the
+    // paper's rod runs use 8 z points, Sec. 6.3): the support then wraps onto
+    // itself and its coinciding points add, which needs one spreading tile to
+    // span the axis (Mz = 8, 12 or 16).
+    const int gxy = grid[0] < grid[1] ? grid[0] : grid[1];
+    if (MG < 2 || MG > kMaxSupport || MG > gxy) return FCM_EINVAL;
+    if (MG > grid[2] && grid[2] != 8 && grid[2] != 12 && grid[2] != 16) return FCM_EINVAL;
     // FP64 spreading stages its particles with M_G-point tables in LDS
     if (opt.precision == FCM_FP64 && MG > 24) return FCM_EINVAL;
     const int mz = fft_maxe(opt.precision, true) * 256;

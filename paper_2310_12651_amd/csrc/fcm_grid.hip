@@ -86,6 +86,7 @@ struct Stage {
     unsigned lm[2][kChunk];
     unsigned km[kChunk];
     int zo[kChunk];
+    int dz[kChunk];      // folded z (support longer than the z axis): (Z0 - first point) mod Mz
     R c[2][kChunk];
     R fz[kChunk];
     R F[3][kChunk];
@@ -147,16 +148,39 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
     auto process = [&]() {
         __syncthreads();
         // their z factors, one table entry per lane
-        for (int e = lane; e < cnt * MG; e += 64) {
-            const int s = (e * a.mgmul) >> 16, t = e - s * MG;
-            const R d = ((R)t - stg.fz[s]) * dx;
-            const R d2 = d * d;
-            ZTab<R> z;
-            z.g = fexp2(-d2 * a.e2);
-            z.gd2 = z.g * d2;
-            z.gD = SAMEW ? z.g : fexp2(-d2 * a.e2D);
-            z.gDd = z.gD * d;
-            zt[e] = z;
+        if (!a.zfold) {
+            for (int e = lane; e < cnt * MG; e += 64) {
+                const int s = (e * a.mgmul) >> 16, t = e - s * MG;
+                const R d = ((R)t - stg.fz[s]) * dx;
+                const R d2 = d * d;
+                ZTab<R> z;
+                z.g = fexp2(-d2 * a.e2);
+                z.gd2 = z.g * d2;
+                z.gD = SAMEW ? z.g : fexp2(-d2 * a.e2D);
+                z.gDd = z.gD * d;
+                zt[e] = z;
+            }
+        } else {
+            // support longer than the z axis (one tile spans it, TZ = Mz):
+            // height k receives the support points t = k + dz (mod Mz),
+            // t + Mz, ... below M_G; their factors are summed into entry k
+            for (int e = lane; e < cnt * Mz; e += 64) {
+                const int s = e / Mz, k = e - s * Mz;
+                int t = k + stg.dz[s];
+                if (t >= Mz) t -= Mz;
+                ZTab<R> z = {0, 0, 0, 0};
+                for (; t < MG; t += Mz) {
+                    const R d = ((R)t - stg.fz[s]) * dx;
+                    const R d2 = d * d;
+                    const R g = fexp2(-d2 * a.e2);
+                    const R gD = SAMEW ? g : fexp2(-d2 * a.e2D);
+                    z.g += g;
+                    z.gd2 += g * d2;
+                    z.gD += gD;
+                    z.gDd += gD * d;
+                }
+                zt[s * MG + k] = z;
+            }
         }
         __syncthreads();
         for (int q = 0; q < cnt; ++q) {
@@ -335,8 +359,16 @@ __global__ __launch_bounds__(64) void k_spread(const GridRec<R>* __restrict__ re
             if (lo2 < TZ) km |= low_bits(hi2) & ~low_bits(lo2);
             stg.lm[0][k] = (unsigned)lm;
             stg.lm[1][k] = (unsigned)(lm >> 32);
+            if (a.zfold) {
+                // every height of the tile (the whole z axis) is in the support;
+                // the contributor's table holds one folded entry per height
+                km = low_bits(TZ);
+                stg.dz[k] = dz0;
+                stg.zo[k] = k * MG * (int)sizeof(ZTab<R>);
+            } else {
+                stg.zo[k] = (k * MG + (hi1 > 0 ? dz0 : dz0 - Mz)) * (int)sizeof(ZTab<R>);
+            }
             stg.km[k] = km;
-            stg.zo[k] = (k * MG + (hi1 > 0 ? dz0 : dz0 - Mz)) * (int)sizeof(ZTab<R>);
             stg.c[0][k] = (R)ox - r.f[0];
             stg.c[1][k] = (R)oy - r.f[1];
             stg.fz[k] = r.f[2];
@@ -452,7 +484,7 @@ __global__ __launch_bounds__(256) void k_interp(const GridRec<R>* __restrict__ r
             (unsigned)sizeof(R);
         for (int k = 0; k < MG; ++k) {
             int z = r.s[2] + k;
-            if (z >= Mz) z -= Mz;
+            while (z >= Mz) z -= Mz;   // the support may be longer than the z axis
             const ZTab<R> e = zt[wave][k];
             const R* pz = grid + (size_t)z * nplane;
             const R u0 = plane_load(pz, nplane, col);
@@ -601,7 +633,7 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
     float P[3] = {0, 0, 0}, Rr[3] = {0, 0, 0}, PD2[3] = {0, 0, 0}, PD[2] = {0, 0}, Q[2] = {0, 0};
     for (int k = 0; k < MG; ++k) {
         int z = r.s[2] + k;
-        if (z >= Mz) z -= Mz;
+        while (z >= Mz) z -= Mz;   // the support may be longer than the z axis
         const ZTab<float> e = zt[wave][k];
         const float* pz = grid + (size_t)z * nplane;
         float4 u[3] = {make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0)};
@@ -853,6 +885,7 @@ GridArgs<R> make_args(const fcm_plan_impl* P) {
     a.backz = P->backz;
     a.mgmul = 65536 / P->MG + 1;
     a.tiled = 0;
+    a.zfold = P->MG > P->Mz ? 1 : 0;
     a.dx = (R)P->dx;
     const double log2e = 1.4426950408889634074;
     a.e2 = (R)(log2e / (2.0 * P->Sigma * P->Sigma));

@@ -97,6 +97,7 @@ struct GridArgs {
     int backx, backy, backz;       // bins scanned before the tile's own
     int mgmul;                     // 65536 / MG + 1: e / MG = (e * mgmul) >> 16 for e < 1024
     int tiled;                     // interp: field in the x-y tiled layout
+    int zfold;                     // M_G > Mz: one tile spans z, support points folded
     R dx;                          // grid spacing
     R e2;                          // log2(e) / (2 Sigma^2)
     R e2D;                         // log2(e) / (2 Sigma_D^2)

@@ -4,7 +4,10 @@ Cases: a box long in x (48 x 18 x 18 points, M_G = 12: the four-lane FP32
 interpolation of the row-major layout), a flat one (48 x 32 x 24, M_G = 16), and a thin one (64 x 64 x
 16, M_G = 16, so spreading tiles are one point high), and a slab whose y period
 equals the support (48 x 12 x 24, M_G = 12: every support covers all of y and the
-spreading tiles are one row wide); every operator and the whole mobility, FP64 (1e-10 normwise) and FP32 bulk (1e-5).  Also the copy
+spreading tiles are one row wide); the paper's rod grid 512 x 512 x 8 with
+M_G = 10 and two more boxes whose support is longer than the z axis (M_G = 12
+on 8 points, M_G = 16 on 12: the support wraps onto itself), and the paper's
+filament grid 256 x 256 x 16; every operator and the whole mobility, FP64 (1e-10 normwise) and FP32 bulk (1e-5).  Also the copy
 identity of the oracle's box pins, on the GPU: copies of a cube along one axis
 keep the cube's velocities.
 """
@@ -28,6 +31,14 @@ BOXES = {
     "flat48x32x24": dict(L=(24.0, 16.0, 12.0), M=(48, 32, 24), Sigma=0.75, M_G=16, R_c=5.0, N=40),
     "thin64x64x16": dict(L=(32.0, 32.0, 8.0), M=(64, 64, 16), Sigma=0.7, M_G=16, R_c=3.5, N=40),
     "slab48x12x24": dict(L=(24.0, 6.0, 12.0), M=(48, 12, 24), Sigma=0.75, M_G=12, R_c=2.9, N=20),
+    # supports longer than the z axis (they wrap onto themselves and their
+    # coinciding points add): the paper's rod grid (Sec. 6.3, 512 x 512 x 8,
+    # M_G = 10 at Sigma = dx), and M_G = 12 on 8 and M_G = 16 on 12 z points
+    "rods512x512x8": dict(L=(512.0, 512.0, 8.0), M=(512, 512, 8), Sigma=1.0, M_G=10, R_c=3.9, N=2000),
+    "fold64x64x8": dict(L=(32.0, 32.0, 4.0), M=(64, 64, 8), Sigma=0.6, M_G=12, R_c=1.95, N=40),
+    "fold48x48x12": dict(L=(24.0, 24.0, 6.0), M=(48, 48, 12), Sigma=0.75, M_G=16, R_c=2.9, N=40),
+    # the paper's filament grid (Sec. 6.3, 256 x 256 x 16)
+    "fil256x256x16": dict(L=(204.8, 204.8, 12.8), M=(256, 256, 16), Sigma=0.8, M_G=10, R_c=4.4, N=1500),
 }
 
 
@@ -75,7 +86,8 @@ def test_box_plan_properties(box):
     plan = _plan(box, "fp64")
     info = plan.box_info()
     assert info["grid"] == tuple(c["M"]) and np.allclose(info["L"], c["L"])
-    assert info["cells"] == tuple(max(int(l / c["R_c"]), 3) for l in c["L"])
+    # m = max(int(L / R_c), 3) per axis (Sec. 4), at most 128 cells per axis
+    assert info["cells"] == tuple(min(max(int(l / c["R_c"]), 3), 128) for l in c["L"])
     assert plan.new_grid().shape == (3, c["M"][2], c["M"][1], c["M"][0])
 
 

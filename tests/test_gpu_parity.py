@@ -189,10 +189,12 @@ def test_mobility_matches_oracle(case, prec):
 def test_optional_torque_and_omega(case, prec):
     """T = NULL means zero torques; Omega = NULL skips angular velocities.
 
-    FP64 meets the plain normwise bar on Omega.  In FP32 Omega from forces
-    alone can nearly cancel (one particle: zero by symmetry up to the grid's
-    discretisation), so its FP32 error is measured against the larger of |Omega|
-    and the angular scale |V| / a of the same forces."""
+    FP64 meets the plain normwise bar on Omega wherever Omega does not cancel.
+    A lone particle's Omega from its force vanishes by symmetry up to the
+    grid's residual (about 1e-9 of the angular scale |V| / a on 64^3): there the
+    rounding of its O(|V| / a) sums bounds the error, in FP64 as in FP32, so the
+    error is measured against that scale.  In FP32 the same scale is taken in
+    every case (single-precision sums cancel to 1e-7 of it)."""
     w = case["w"]
     p = case["p"]
     tol = PREC[prec][1]
@@ -200,10 +202,11 @@ def test_optional_torque_and_omega(case, prec):
     V, W = plan.mobility(dev(w["Y"]), dev(w["F"]), None)
     Vr, Wr = ff.mobility(p, w["Y"], w["F"], None)
     assert normwise(host(V), Vr) < tol
-    if prec == "fp64":
+    ang = np.linalg.norm(Vr) / w["a"]
+    if prec == "fp64" and np.linalg.norm(Wr) > 1e-6 * ang:
         assert normwise(host(W), Wr) < 1e-10
     else:
-        scale = max(np.linalg.norm(Wr), np.linalg.norm(Vr) / w["a"])
+        scale = max(np.linalg.norm(Wr), ang)
         assert np.linalg.norm(host(W) - Wr) < tol * scale
     V2, W2 = plan.mobility(dev(w["Y"]), dev(w["F"]), dev(w["T"]), want_omega=False)
     assert W2 is None and normwise(host(V2), case["V"]) < tol
