@@ -52,7 +52,8 @@ enum {
     FCM_ENOMEM = -2,      /* device or host allocation failed                      */
     FCM_EDEVICE = -3,     /* a HIP runtime call failed                             */
     FCM_ERANGE = -4,      /* r_cut >= L/2: pairs would need more than one image    */
-    FCM_ENONFINITE = -5   /* non-finite input seen by the last call (see below)    */
+    FCM_ENONFINITE = -5,  /* non-finite input seen by the last call (see below)    */
+    FCM_ESCRATCH = -7     /* too large for fcm_mobility_static's 64 MiB scratch    */
 };
 
 /* Precision of the grid part (spreading, FFT Stokes solve, interpolation).
@@ -127,6 +128,27 @@ int fcm_plan_destroy(fcm_plan_t p);
  */
 int fcm_mobility(fcm_plan_t p, const double* pos, const double* F, const double* T,
                  double* V, double* Omega, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): fcm_mobility without a
+ * plan.  The arguments are those of fcm_plan_ex followed by those of
+ * fcm_mobility (opt may be NULL for the defaults); the results equal those of
+ * fcm_mobility on a plan built with the same arguments, to rounding (1e-10
+ * relative in FP64, 1e-5 in FP32 bulk).
+ * Memory: no allocation of any kind.  Every buffer of the evaluation (field,
+ * sort arrays, records, neighbour lists, corrections) lives in a static device
+ * array of 64 MiB that each GPU the library runs on holds until the process
+ * ends; the pair correction runs on `stream` itself (no side stream).  That
+ * bounds the problem: e.g. 10^4 particles on a 128^3 FP32 grid fit.
+ * Concurrency: every call on one GPU uses that GPU's single array, so calls
+ * that overlap on one GPU (other streams, other threads) race; serialise them.
+ * Errors: as fcm_plan_ex and fcm_mobility; FCM_ESCRATCH if the buffers the
+ * problem needs exceed the array (nothing is launched then).
+ */
+int fcm_mobility_static(int64_t N, double L, double a, double sigma_delta, int grid, double r_cut,
+                        const fcm_options* opt, const double* pos, const double* F, const double* T,
+                        double* V, double* Omega, void* stream);
 
 /*
  * The mobility again at the positions of this plan's last fcm_mobility call,

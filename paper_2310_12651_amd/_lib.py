@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcm.so")
 
 FCM_OK, FCM_EINVAL, FCM_ENOMEM, FCM_EDEVICE, FCM_ERANGE, FCM_ENONFINITE = 0, -1, -2, -3, -4, -5
+FCM_ESCRATCH = -7
 FCM_FP64, FCM_FP32_BULK = 0, 1
 
 EXPORTS = [
@@ -20,7 +21,7 @@ EXPORTS = [
     "fcm_plan_destroy", "fcm_mobility",
     "fcm_mobility_repeat", "fcm_brownian", "fcm_brownian_reserve", "fcm_spread", "fcm_solve", "fcm_interp", "fcm_correct", "fcm_plan_info",
     "fcm_plan_footprint", "fcm_plan_footprint_box", "fcm_plan_last_error", "fcm_status_string", "fcm_plan_set_timing",
-    "fcm_plan_stage_times",
+    "fcm_plan_stage_times", "fcm_mobility_static",
 ]
 STAGES = ["sort", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_solve", "fft_y_inv", "fft_x_inv",
           "interp", "pair"]
@@ -79,6 +80,8 @@ def library():
         "fcm_status_string": ([ci], ctypes.c_char_p),
         "fcm_plan_set_timing": ([vp, ci], ci),
         "fcm_plan_stage_times": ([vp, ctypes.POINTER(cd), ctypes.POINTER(ci)], ci),
+        "fcm_mobility_static": ([i64, cd, cd, cd, ci, cd, ctypes.POINTER(Options), dp, dp, dp, dp, dp, vp],
+                                ci),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -148,6 +151,29 @@ def fcm_plan_footprint_box(N, L, a, Sigma, grid, r_cut, options=None):
     _check(library().fcm_plan_footprint_box(int(N), L3, float(a), float(Sigma), g3, float(r_cut), opt,
                                             ctypes.byref(b)), "fcm_plan_footprint_box")
     return b.value
+
+
+def mobility_static(N, L, a, Sigma, grid, r_cut, pos, F, T=None, V=None, Omega=None, eta=1.0, support=0,
+                    sigma_D_grid=0.0, precision=FCM_FP32_BULK, kahan=0, stream=None, want_omega=True):
+    """fcm_mobility_static: the mobility without a plan, in the library's
+    static device scratch (no allocation by the library; V and Omega are
+    allocated here unless given)."""
+    import torch
+    N = int(N)
+    if V is None:
+        V = torch.empty((N, 3), dtype=torch.float64, device=pos.device)
+    if Omega is None and want_omega:
+        Omega = torch.empty((N, 3), dtype=torch.float64, device=pos.device)
+    o = fcm_options_default()
+    o.eta, o.support, o.sigma_D_grid = float(eta), int(support), float(sigma_D_grid)
+    o.precision, o.kahan = int(precision), int(kahan)
+    f64 = torch.float64
+    _check(library().fcm_mobility_static(N, float(L), float(a), float(Sigma), int(grid), float(r_cut),
+                                         ctypes.byref(o), _ptr(pos, "pos", N, f64), _ptr(F, "F", N, f64),
+                                         _ptr(T, "T", N, f64, True), _ptr(V, "V", N, f64),
+                                         _ptr(Omega, "Omega", N, f64, True), _stream(stream)),
+           "fcm_mobility_static")
+    return V, Omega
 
 
 class Plan:

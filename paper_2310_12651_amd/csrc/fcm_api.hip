@@ -7,11 +7,18 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "fcm_internal.h"
 
 using namespace fcm;
+
+// Device scratch of the allocation-free entry point fcm_mobility_static: one
+// 64 MiB array per GPU the library runs on (uninitialised; the code object
+// carries only its size).  Host code uses its device address, never its name.
+constexpr int64_t kStaticScratchBytes = (int64_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -441,6 +448,109 @@ int64_t plan_bytes(int64_t ncap, const int grid[3], int precision, int cellcap, 
 
 }  // namespace fcm
 
+namespace {
+
+// ---- the allocation-free entry point (fcm_mobility_static) ----------------
+//
+// Every buffer of its plan lives in `scratch`, one array per GPU the library
+// runs on, held until the process ends.  Host code never passes the array's
+// name to the device: it takes the array's device address once per device
+// (hipGetSymbolAddress, with that device current) and uses that address.
+
+constexpr int kMaxStaticDevices = 64;
+
+std::mutex g_static_mu;
+unsigned char* g_static_ptr[kMaxStaticDevices];
+
+// the device address of this device's scratch (looked up on first use)
+int static_scratch(unsigned char** out, int* device) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FCM_EDEVICE;
+    if (dev < 0 || dev >= kMaxStaticDevices) return FCM_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FCM_EDEVICE;
+        g_static_ptr[dev] = (unsigned char*)ptr;
+    }
+    *out = g_static_ptr[dev];
+    *device = dev;
+    return FCM_OK;
+}
+
+// the buffers of plan_allocate, carved in the same order from `base` (each
+// 256-byte aligned; plan_bytes(...) plus the alignment fits the scratch, see
+// the size check at the call); no side stream, events or timing
+void carve_static_plan(fcm_plan_impl* P, unsigned char* base) {
+    const int64_t ncap = P->N;
+    const int cellcap = P->ncells;
+    P->Ncap = ncap;
+    P->cells_cap = cellcap;
+    const size_t rs = real_size(P->precision);
+    const size_t M3 = (size_t)P->M * P->My * P->Mz;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        void* p = base + off;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    P->grid = take(3 * M3 * rs);
+    P->twid = take((size_t)(P->M + P->My + P->Mz) * 2 * rs);
+    P->counts = (int*)take((size_t)(P->nbins + cellcap) * sizeof(int));
+    P->starts = (int*)take((size_t)(P->nbins + 1 + cellcap + 1) * sizeof(int));
+    P->keys = (int*)take((size_t)2 * ncap * sizeof(int));
+    P->ranks = (int*)take((size_t)2 * ncap * sizeof(int));
+    P->perm = (int*)take((size_t)2 * ncap * sizeof(int));
+    P->scan_tmp = (int*)take(kMaxScanTiles * sizeof(int));
+    P->grec = take((size_t)ncap * grid_rec_size(P->precision));
+    P->prec = (PairRec*)take((size_t)ncap * sizeof(PairRec));
+    P->ppos = (double4*)take((size_t)ncap * sizeof(double4));
+    P->pair_hits = (int*)take((size_t)3 * ncap * kPairCap * sizeof(int));
+    P->pair_count = (int*)take((size_t)3 * ncap * sizeof(int));
+    P->corr = (double*)take((size_t)6 * ncap * sizeof(double));
+    P->partial = (double*)take(1024 * sizeof(double));
+    P->flag = (int*)take(16 * sizeof(int));
+    P->side = nullptr;
+    P->fork = P->join = nullptr;
+    P->timing = 0;
+    P->events = nullptr;
+}
+
+// twiddles exp(-2 pi i m / n) for n = M, My, Mz in turn (FP64 sincospi,
+// rounded once to the grid precision)
+template <typename R>
+__global__ void k_static_twiddles(R* __restrict__ tw, int M, int My, int Mz) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M + My + Mz) return;
+    int n = M, m = t;
+    if (m >= M) {
+        m -= M;
+        n = My;
+        if (m >= My) {
+            m -= My;
+            n = Mz;
+        }
+    }
+    double sn, cs;
+    sincospi(-2.0 * (double)m / (double)n, &sn, &cs);
+    tw[2 * t] = (R)cs;
+    tw[2 * t + 1] = (R)sn;
+}
+
+hipError_t launch_static_twiddles(const fcm_plan_impl* P, hipStream_t st) {
+    const int n = P->M + P->My + P->Mz;
+    const int blocks = (n + 255) / 256;
+    if (P->precision == FCM_FP64)
+        hipLaunchKernelGGL(k_static_twiddles<double>, dim3(blocks), dim3(256), 0, st, (double*)P->twid, P->M,
+                           P->My, P->Mz);
+    else
+        hipLaunchKernelGGL(k_static_twiddles<float>, dim3(blocks), dim3(256), 0, st, (float*)P->twid, P->M,
+                           P->My, P->Mz);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 extern "C" {
 
 int fcm_options_default(fcm_options* opt) {
@@ -557,7 +667,11 @@ hipError_t mobility_from_records(fcm_plan_impl* p, const double* T, double* V, d
     // The pair correction depends only on the sorted records: it runs on the
     // plan's side stream while spread and FFT run here, into the plan's
     // correction buffer, which the interpolation adds to its results.
-    if (corr) {
+    if (corr && !p->side) {
+        // a plan without a side stream (the static entry point) runs the pair
+        // correction on the call's stream, before the grid part
+        e = launch_pair(p, p->corr, Omega ? p->corr + 3 * p->N : nullptr, T != nullptr, st, true, scan);
+    } else if (corr) {
         e = hipEventRecord(p->fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
         if (ev && e == hipSuccess && timing_event(p, 10)) (void)hipEventRecord(ev[10], p->side);
@@ -575,7 +689,7 @@ hipError_t mobility_from_records(fcm_plan_impl* p, const double* T, double* V, d
     const bool tiled = solve_tiles(p);
     if (e == hipSuccess) e = launch_spread(p, T != nullptr, p->grid, st, tiled);
     if (e == hipSuccess) e = launch_solve(p, p->grid, st, ev ? ev + 2 : nullptr, tiled);
-    if (e == hipSuccess && corr) e = hipStreamWaitEvent(st, p->join, 0);
+    if (e == hipSuccess && corr && p->side) e = hipStreamWaitEvent(st, p->join, 0);
     if (e == hipSuccess) e = launch_interp(p, p->grid, V, Omega, st, tiled, corr ? p->corr : nullptr);
     return e;
 }
@@ -802,6 +916,37 @@ int fcm_plan_last_error(fcm_plan_t p) {
     return FCM_OK;
 }
 
+int fcm_mobility_static(int64_t N, double L, double a, double sigma_delta, int grid, double r_cut,
+                        const fcm_options* opt, const double* pos, const double* F, const double* T,
+                        double* V, double* Omega, void* stream) {
+    if (!pos || !F || !V) return FCM_EINVAL;
+    fcm_plan_impl P;
+    const double L3[3] = {L, L, L};
+    const int g3[3] = {grid, grid, grid};
+    int st = plan_derive(&P, N, L3, a, sigma_delta, g3, r_cut, opt);
+    if (st != FCM_OK) return st;
+    // the buffers, each rounded up to 256 bytes, must fit the scratch
+    if (plan_bytes(N, g3, P.precision, P.ncells, P.nbins) + 16 * 256 > kStaticScratchBytes)
+        return FCM_ESCRATCH;
+    unsigned char* base = nullptr;
+    st = static_scratch(&base, &P.device);
+    if (st != FCM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    carve_static_plan(&P, base);
+    // The scratch keeps the last call's contents: the counters (cleared by the
+    // sort, as after a plan's allocation) and the flags must start at zero, and
+    // the twiddles are rebuilt for this grid.
+    P.counts_dirty = 1;
+    hipError_t e = launch_fill(P.flag, 16, 0, s);
+    if (e == hipSuccess) e = launch_static_twiddles(&P, s);
+    const bool corr = needs_correction(&P);
+    if (e == hipSuccess) e = sort_particles(&P, pos, s);
+    if (e == hipSuccess)
+        e = corr ? launch_gather_both(&P, pos, F, T, s) : launch_gather_grid(&P, pos, F, T, s);
+    if (e == hipSuccess) e = mobility_from_records(&P, T, V, Omega, s, nullptr, true);
+    return map_err(e);
+}
+
 const char* fcm_status_string(int status) {
     switch (status) {
         case FCM_OK: return "ok";
@@ -810,6 +955,7 @@ const char* fcm_status_string(int status) {
         case FCM_EDEVICE: return "HIP runtime error";
         case FCM_ERANGE: return "cut-off radius must be below half the box";
         case FCM_ENONFINITE: return "non-finite position in the last call";
+        case FCM_ESCRATCH: return "problem needs more than the static scratch of fcm_mobility_static (64 MiB per GPU)";
         default: return "unknown status";
     }
 }
