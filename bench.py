@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--tune-sigma", action="store_true",
                     help="instead of the headline run: evaluations/s against Sigma/sigma at "
                          "a/L = 1/400 for the volume fractions of Table 3 (its optimum on this GPU)")
+    ap.add_argument("--paper-grids", action="store_true",
+                    help="call times on the grids of the paper's Sec. 6.3 runs (512x512x8, 256x256x16)")
     ap.add_argument("--brownian", action="store_true",
                     help="instead of the headline run: time fcm_brownian on the workload (FP32 bulk "
                          "and FP64, Lanczos tolerance 1e-6)")
@@ -554,6 +556,64 @@ def tune_sigma(args, torch):
                                         "for phi 0.05, 0.2, 0.8, 3.2, 12.8 %; peak ~7e6 PTPS")
 
 
+def paper_grids(args, torch):
+    """Call times of the mobility on the grids of the paper's Sec. 6.3
+    scaling runs (Fig. 8), as the number of bodies grows at a fixed domain:
+    planar rod suspensions in a 3840a x 3840a x 60a box on 512 x 512 x 8
+    points (dx = 7.5a, Sigma = dx, M_G = 10, so the support wraps once around
+    z), and tethered filaments in 5760a x 5760a x 360a on 256 x 256 x 16
+    points (dx = 22.5a, Sigma = dx, M_G = 10).  R_c = 6 Sigma as in the paper
+    for the filaments; for the rods it is held below half the 60a height
+    (29.9a = 3.99 Sigma), since the pair correction takes one image per pair.
+    Rods: 22 spheres each (touching spheres of spacing 2a stand in for the
+    paper's doublets); filaments: 20 segments of spacing 2.2a.  F, T ~ N(0, 1)."""
+    import numpy as np
+
+    import workloads
+    from paper_2310_12651_amd import FCM_FP32_BULK, FCM_FP64, Plan
+    rng = np.random.default_rng(workloads.SEED_BASE + 7)
+    dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    out = {"rods_512x512x8": [], "filaments_256x256x16": []}
+    cases = [("rods_512x512x8", n, (3840.0, 3840.0, 60.0), (512, 512, 8), 29.9) for n in (576, 2304, 7744)]
+    cases += [("filaments_256x256x16", n, (5760.0, 5760.0, 360.0), (256, 256, 16), 6 * 22.5)
+              for n in (100, 400, 1600, 6400)]
+    for key, nb, L, grid, rc in cases:
+        if key.startswith("rods"):
+            Y = workloads.rod_monolayer(nb, 22, L[0], 0.5 * L[2], 1.0, rng)
+        else:
+            Y = workloads.filament_array(nb, 20, L[0], 2.2, 1.0, rng)
+        N = len(Y)
+        F, T = rng.normal(size=(N, 3)), rng.normal(size=(N, 3))
+        Yd, Fd, Td = dev(Y), dev(F), dev(T)
+        V = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+        W = torch.empty_like(V)
+        row = {"bodies": nb, "N": N}
+        for name, prec in (("fp32", FCM_FP32_BULK), ("fp64", FCM_FP64)):
+            plan = Plan(N, L, 1.0, L[0] / grid[0], grid, rc, support=10, precision=prec)
+            for _ in range(3):
+                plan.mobility(Yd, Fd, Td, V, W)
+            plan.set_timing(True)
+            for _ in range(5):
+                plan.mobility(Yd, Fd, Td, V, W)
+            stages, nc = plan.stage_times()
+            plan.set_timing(False)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                plan.mobility(Yd, Fd, Td, V, W)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            row[name] = {"ms_per_call": round(ms, 4), "evals_per_s": N / (ms * 1e-3),
+                         "stages_ms": {k: round(v / max(nc, 1), 4) for k, v in stages.items()}}
+            plan.close()
+        log(f"[bench] {key} bodies={nb} N={N}: fp32 {row['fp32']['ms_per_call']:.3f} ms, "
+            f"fp64 {row['fp64']['ms_per_call']:.3f} ms")
+        out[key].append(row)
+    return out
+
+
 def brownian_leg(args, torch):
     """Brownian velocities (fcm_brownian) on the workload: ms per call for FP32
     bulk and FP64 with seeded noise (grid noise in the grid precision), the
@@ -612,6 +672,9 @@ def main():
 
     if args.brownian:
         print(json.dumps(brownian_leg(args, torch)), flush=True)
+        return
+    if args.paper_grids:
+        print(json.dumps(paper_grids(args, torch)), flush=True)
         return
     if args.tune_sigma:
         print(json.dumps(tune_sigma(args, torch)), flush=True)

@@ -124,6 +124,54 @@ def rod_positions(n_rods, per_rod, L, a, rng, max_tries=200):
     return out
 
 
+def rod_monolayer(n_rods, per_rod, Lxy, z0, a, rng):
+    """A planar suspension of rods (the setting of the paper's rod runs, Sec.
+    6.1): rod centres on a square lattice of the [0, Lxy)^2 plane at height
+    z0, each rod turned by a uniform angle within the plane.  A rod is
+    ``per_rod`` (even) spheres stacked as doublets: per_rod / 2 stations
+    along the axis, spacing a sqrt(2), each holding two spheres offset by
+    +-a/sqrt(2), the doublets alternating between the in-plane normal and z
+    (length (per_rod/2 - 1) a sqrt(2) + 2a: 16.1a for 22 spheres)."""
+    side = int(math.ceil(math.sqrt(n_rods)))
+    s = Lxy / side
+    ns = per_rod // 2
+    length = (ns - 1) * a * math.sqrt(2.0) + 2.0 * a
+    if s <= length:
+        raise ValueError("rods too long for the lattice spacing")
+    ax = (np.arange(ns) - 0.5 * (ns - 1)) * a * math.sqrt(2.0)
+    h = a / math.sqrt(2.0)
+    out = np.empty((n_rods * per_rod, 3))
+    for r in range(n_rods):
+        th = rng.uniform(0.0, 2.0 * math.pi)
+        c = np.array([(r % side + 0.5) * s, (r // side + 0.5) * s, z0])
+        u = np.array([math.cos(th), math.sin(th), 0.0])
+        nrm = np.array([-math.sin(th), math.cos(th), 0.0])
+        ez = np.array([0.0, 0.0, 1.0])
+        pts = []
+        for i in range(ns):
+            d = nrm if i % 2 == 0 else ez
+            pts.append(c + ax[i] * u + h * d)
+            pts.append(c + ax[i] * u - h * d)
+        out[r * per_rod:(r + 1) * per_rod] = np.array(pts)
+    return out
+
+
+def filament_array(n_fil, per_fil, Lxy, dl, a, rng):
+    """Filaments tethered on a square lattice of the plane z = 0 (the setting
+    of the paper's filament runs, Sec. 6.2): ``per_fil`` segments spaced dl
+    along a direction tilted from the z axis by up to 30 degrees."""
+    side = int(math.ceil(math.sqrt(n_fil)))
+    s = Lxy / side
+    out = np.empty((n_fil * per_fil, 3))
+    for f in range(n_fil):
+        th = rng.uniform(0.0, math.pi / 6.0)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        u = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        base = np.array([(f % side + 0.5) * s, (f // side + 0.5) * s, a])
+        out[f * per_fil:(f + 1) * per_fil] = base[None, :] + (np.arange(per_fil) * dl)[:, None] * u[None, :]
+    return out
+
+
 def box_for_fraction(N, a, phi):
     """Side L of the cube holding N spheres of radius a at volume fraction phi."""
     return (N * 4.0 * math.pi * a ** 3 / 3.0 / phi) ** (1.0 / 3.0)
