@@ -343,7 +343,7 @@ def compare_standard(args, torch):
         for phi in phis:
             N = int(round(phi * L ** 3 / (4.0 * math.pi * a ** 3 / 3.0)))
             rng = np.random.default_rng(workloads.SEED_BASE + 2000 + int(1e4 * al) + int(1e3 * phi))
-            Yh = workloads.lattice_positions(N, L, a, rng)
+            Yh, kind = suspension_positions(N, L, a, phi, rng)
             Fh = rng.normal(size=(N, 3))
             Y = torch.as_tensor(Yh, device="cuda")
             F = torch.as_tensor(Fh, device="cuda")
@@ -369,14 +369,14 @@ def compare_standard(args, torch):
                     best = (t, Sig, M, V.clone())
             t_fast, Sig, M, V_fast = best
             dv = torch.linalg.vector_norm(V_fast - V_std, dim=1) / torch.linalg.vector_norm(V_std, dim=1)
-            row = dict(a_over_L=al, phi=phi, N=N, L=L,
+            row = dict(a_over_L=al, phi=phi, N=N, L=L, positions=kind,
                        standard=dict(grid=Ms, ms=t_std, ptps=N / (t_std * 1e-3)),
                        fast=dict(grid=M, Sigma_over_sigma=Sig / sigma, R_c=5.5 * Sig, ms=t_fast,
                                  ptps=N / (t_fast * 1e-3)),
                        ratio=t_std / t_fast, eps_fast_vs_standard=float(dv.mean()))
             rows.append(row)
             ratios.append(row["ratio"])
-            log(f"[compare] a/L={al} phi={phi} N={N}: standard {Ms}^3 {t_std:.3f} ms, fast "
+            log(f"[compare] a/L={al} phi={phi} N={N} ({kind}): standard {Ms}^3 {t_std:.3f} ms, fast "
                 f"{M}^3 Sigma/sigma={Sig / sigma:.2f} {t_fast:.3f} ms, ratio {row['ratio']:.2f}, "
                 f"eps {row['eps_fast_vs_standard']:.2e}")
             del Y, F, V, V_std, V_fast
@@ -399,6 +399,20 @@ def compare_standard(args, torch):
                               "phi_c ~ -9.24 a/L + 0.22")
 
 
+# random sequential addition, the paper's random suspensions (Sec. 5), is used
+# where it converges within seconds on the host: up to 16 % volume fraction and
+# 2e5 spheres; denser or larger suspensions use the jittered lattice
+RSA_MAX_PHI, RSA_MAX_N = 0.16, 200_000
+
+
+def suspension_positions(N, L, a, phi, rng):
+    """(positions, 'rsa' | 'lattice') of N spheres in the cube of side L."""
+    import workloads
+    if phi <= RSA_MAX_PHI + 1e-12 and N <= RSA_MAX_N:
+        return workloads.rsa_positions(N, L, a, rng), "rsa"
+    return workloads.lattice_positions(N, L, a, rng), "lattice"
+
+
 def calibrate(args, torch):
     """The error calibration of Sec. 5.1 redone for this library (FP64 path,
     force only, eps = mean_n |V_n - U_n| / |U_n|), in the paper's setting: a
@@ -410,14 +424,16 @@ def calibrate(args, torch):
     Table 2: eps over Sigma/sigma and R_c = lambda Sigma with the grid resolved
     (Sigma/dx = 1.6, M_G = 24) at phi = 4, 8, 16, 32 %; per tolerance the
     smallest lambda (interpolated in log eps) that reaches it, per Sigma and
-    the largest over Sigma.  Positions: the jittered lattice of the request
-    stream; F ~ N(0, 1)."""
+    the largest over Sigma.  Positions: random sequential addition (the
+    paper's random suspensions) up to phi = 16 %, the jittered lattice at 32 %;
+    F ~ N(0, 1)."""
     import numpy as np
 
     import workloads
     from paper_2310_12651_amd import FCM_FP64, Plan
     a, sigma, L = 1.0, 1.0 / math.sqrt(math.pi), 150.0
     tols = (1e-2, 1e-3, 1e-4, 1e-6, 1e-8)
+    kinds = {}
 
     def grid_for(ratio, Sigma0):
         M = workloads.smooth_grid(int(math.ceil(L * ratio / Sigma0 - 1e-9)))
@@ -436,7 +452,8 @@ def calibrate(args, torch):
     def suspension(phi, seed):
         N = int(round(phi * L ** 3 / (4.0 * math.pi * a ** 3 / 3.0)))
         rng = np.random.default_rng(workloads.SEED_BASE + seed)
-        Yh = workloads.lattice_positions(N, L, a, rng)
+        Yh, kind = suspension_positions(N, L, a, phi, rng)
+        kinds[phi] = kind
         return N, torch.as_tensor(Yh, device="cuda"), torch.as_tensor(rng.normal(size=(N, 3)), device="cuda")
 
     def first_below(xs, es, tol):
@@ -492,9 +509,9 @@ def calibrate(args, torch):
             vals = [v for v in each.values() if v is not None]
             rows.append(dict(eps=tol, lambda_max=max(vals) if len(vals) == len(sfacs) else None,
                              per_Sigma=each))
-        table2[str(phi)] = dict(N=N, rows=rows)
+        table2[str(phi)] = dict(N=N, positions=kinds[phi], rows=rows)
     return dict(metric="error calibration of the FP64 path (Tables 1-2 of Sec. 5.1)",
-                table1=table1, table1_eps={f"{r},{mg}": e for (r, mg), e in t1.items()},
+                table1_positions=kinds.get(0.08), table1=table1, table1_eps={f"{r},{mg}": e for (r, mg), e in t1.items()},
                 table2=table2,
                 paper_context=dict(table1=[[1e-2, 0.71, 8], [1e-3, 0.87, 9], [1e-4, 0.99, 10],
                                            [1e-6, 1.20, 12], [1e-8, 1.39, 14]],
