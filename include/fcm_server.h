@@ -14,8 +14,10 @@
  * least recently used first, when the budget needs room.
  *
  * Admission: requests are taken in arrival order, except that one waiting for
- * device memory held by running requests may be passed by later requests that
- * fit, at most 32 times; after that nothing is admitted past it.
+ * device memory held by running requests (or, with max_points, for grid points
+ * in flight) may be passed by later requests that fit, at most 32 times; after
+ * that nothing is admitted past it.  max_points bounds the grid work in flight,
+ * so that a large request is not slowed by as many others as there are slots.
  *
  * Ownership and ordering: request arrays are caller-owned DEVICE pointers
  * (N x 3 FP64, as in fcm_mobility) that must stay valid, and must not be
@@ -67,6 +69,8 @@ typedef struct {
     int precision;       /* FCM_FP64 or FCM_FP32_BULK (default)              */
     int kahan;           /* as fcm_options.kahan (default 0)                 */
     int max_queue;       /* pending requests accepted (default 4096)         */
+    int64_t max_points;  /* grid points of the requests in flight at most;   */
+                         /* 0 = no limit (default); one request always runs  */
 } fcm_server_options;
 
 typedef struct {

@@ -57,6 +57,7 @@ struct Slot {
     int* nonfinite = nullptr;    // pinned host word: the plan's non-finite flag after the call
     Req* req = nullptr;
     CachedPlan* plan = nullptr;
+    int64_t points = 0;          // grid points of the running request
 };
 
 }  // namespace
@@ -77,6 +78,7 @@ struct fcm_server_impl {
     uint64_t use_clock = 0;
     bool stopping = false;
     int inflight = 0;
+    int64_t inflight_points = 0;   // grid points of the requests in flight
     fcm_server_stats stats;
     std::thread worker;
 
@@ -214,6 +216,8 @@ bool fcm_server_impl::retire_locked() {
         s.req = nullptr;
         s.plan = nullptr;
         --inflight;
+        inflight_points -= s.points;
+        s.points = 0;
         any = true;
     }
     if (any) done_cv.notify_all();
@@ -245,7 +249,11 @@ bool fcm_server_impl::admit_locked() {
         fcm_plan_impl d;
         int st = derive_request(opt, r->r, &d);
         CachedPlan* c = nullptr;
-        if (st == FCM_OK) c = plan_for_locked(d, &st);
+        const int64_t pts = st == FCM_OK ? (int64_t)d.M * d.My * d.Mz : 0;
+        // the grid points in flight stay within max_points (one request always runs)
+        const bool crowded = st == FCM_OK && opt.max_points > 0 && inflight > 0 &&
+                             inflight_points + pts > opt.max_points;
+        if (st == FCM_OK && !crowded) c = plan_for_locked(d, &st);
         if (!c && st == FCM_OK) {        // needs room held by running requests
             if (r->bypassed >= kMaxBypass) break;   // admit nothing past it
             ++i;
@@ -290,6 +298,8 @@ bool fcm_server_impl::admit_locked() {
         } else {
             free_slot->req = r;
             free_slot->plan = c;
+            free_slot->points = pts;
+            inflight_points += pts;
             ++inflight;
             if (inflight > stats.inflight_peak) stats.inflight_peak = inflight;
         }
@@ -322,6 +332,7 @@ int fcm_server_options_default(fcm_server_options* o) {
     o->precision = FCM_FP32_BULK;
     o->kahan = 0;
     o->max_queue = 4096;
+    o->max_points = 0;
     return FCM_OK;
 }
 
@@ -331,7 +342,8 @@ int fcm_server_create(fcm_server_t* out, const fcm_server_options* opt_in) {
     fcm_server_options o;
     fcm_server_options_default(&o);
     if (opt_in) o = *opt_in;
-    if (o.slots < 1 || o.slots > 64 || o.max_queue < 1 || o.max_bytes < 0) return FCM_EINVAL;
+    if (o.slots < 1 || o.slots > 64 || o.max_queue < 1 || o.max_bytes < 0 || o.max_points < 0)
+        return FCM_EINVAL;
     if (o.precision != FCM_FP64 && o.precision != FCM_FP32_BULK) return FCM_EINVAL;
     if (o.kahan < 0 || o.kahan > 2) return FCM_EINVAL;
     fcm_server_impl* s = new (std::nothrow) fcm_server_impl;

@@ -23,7 +23,7 @@ class Request(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("max_bytes", ctypes.c_int64), ("slots", ctypes.c_int), ("precision", ctypes.c_int),
-                ("kahan", ctypes.c_int), ("max_queue", ctypes.c_int)]
+                ("kahan", ctypes.c_int), ("max_queue", ctypes.c_int), ("max_points", ctypes.c_int64)]
 
 
 class ServerStats(ctypes.Structure):
@@ -69,11 +69,14 @@ def _check(st, where):
 class Server:
     """Continuous-batching request server on the current device."""
 
-    def __init__(self, slots=8, precision=FCM_FP32_BULK, kahan=0, max_bytes=0, max_queue=4096):
+    def __init__(self, slots=8, precision=FCM_FP32_BULK, kahan=0, max_bytes=0, max_queue=4096,
+                 max_points=None):
         lib = _lib()
         o = ServerOptions()
         _check(lib.fcm_server_options_default(ctypes.byref(o)), "fcm_server_options_default")
         o.slots, o.precision, o.kahan, o.max_bytes, o.max_queue = slots, precision, kahan, max_bytes, max_queue
+        if max_points is not None:
+            o.max_points = int(max_points)
         h = ctypes.c_void_p()
         _check(lib.fcm_server_create(ctypes.byref(h), ctypes.byref(o)), "fcm_server_create")
         self._h = h
