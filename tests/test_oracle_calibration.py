@@ -25,6 +25,7 @@ import numpy as np
 import pytest
 
 import workloads
+from golden_tables import table
 from oracle import fastfcm as ff
 
 A = 1.0
@@ -62,7 +63,12 @@ def reference(suspension):
     return _velocities(suspension, 2.0 * SIG, 1.6, 24, R_c=0.499 * suspension["L"])
 
 
-@pytest.mark.parametrize("ratio, MG, eps", [(0.71, 8, 1e-2), (0.87, 9, 1e-3), (0.99, 10, 1e-4)])
+# the paper's printed rows (tests/golden/, Sec. 5.1 Table 1 and Sec. 5.2 Table 2)
+T1 = table("table1_grid_resolution.txt")
+T2 = table("table2_cutoff_slope.txt")
+
+
+@pytest.mark.parametrize("ratio, MG, eps", [(r[1], int(r[2]), r[0]) for r in T1 if r[0] >= 1e-4])
 def test_table1_grid_resolution_rows(suspension, reference, ratio, MG, eps):
     """Table 1: the grid part at (Sigma/dx, M_G) of a row, all pairs corrected."""
     V = _velocities(suspension, 2.0 * SIG, ratio, MG, R_c=0.499 * suspension["L"])
@@ -78,11 +84,16 @@ def test_table1_error_falls_with_resolution(suspension, reference):
     assert e_dx > 5 * e0 and e_mg > 5 * e0
 
 
-@pytest.mark.parametrize("lam, eps", [(2.47, 1e-2), (3.66, 1e-3), (5.08, 1e-4), (7.18, 1e-6),
-                                      (8.57, 1e-8)])
+@pytest.mark.parametrize("lam, eps", [(r[2], r[0]) for r in T2])   # the phi = 8 % column
 def test_table2_cutoff_slope_rows(suspension, reference, lam, eps):
     """Table 2 (phi = 8 %): R_c = lambda_eps Sigma with the grid resolved
     (Sigma/dx = 1.6, M_G = 20) gives an error of the row's size."""
     V = _velocities(suspension, 2.0 * SIG, 1.6, 20, lam=lam)
     e = _eps(V, reference)
     assert eps / 3.0 < e < 3.0 * eps, e
+
+
+def test_request_stream_uses_table3():
+    """The request stream's width rule is Table 3's optimum (Sec. 5.2)."""
+    T3 = table("table3_optimal_width.txt")
+    assert np.allclose(workloads._T3_PHI, T3[:, 0]) and np.allclose(workloads._T3_RATIO, T3[:, 1])
