@@ -604,6 +604,204 @@ __global__ __launch_bounds__(W * N2) void k_fft_z_solve_reg(C2<float>* __restric
         for (int i = 0; i < N1; ++i) buf_store(v[c][i], rs, lo, c * cstride + i * N2 * zstride);
 }
 
+// z pass with one thread group per component: W kx columns at one ky, N2
+// threads per column and component (3 W N2 threads).  Each thread transforms
+// one component's line; the projection runs on the tile in LDS with the
+// arithmetic of k_fft_z_solve_reg for each element.  A thread holds N1
+// values instead of 3 N1, so the lines of 216-432 points fit in registers.
+template <int N1, int N2, int W>
+struct ZGeom3 {
+    static constexpr int M = N1 * N2;
+    static constexpr int H = M / 2;
+    static constexpr int GT = W * N2;        // threads per component group
+    static constexpr int NT = 3 * GT;        // threads per block
+    static constexpr int PL = N2 * W + 8;    // exchange-buffer stride of k1 (complex)
+    static constexpr int EL = N1 * PL;       // one component's exchange buffer
+    static constexpr int NG = H / W;         // column groups per kx row
+    static_assert(H % W == 0, "W must divide M/2");
+    static_assert(NT <= 1024, "block size");
+};
+
+template <int N1, int N2, int W>
+__global__ __launch_bounds__(3 * W * N2) void k_fft_z_solve_3g(
+    C2<float>* __restrict__ spec, const C2<float>* __restrict__ twg, ProjArgs pa) {
+    using G = ZGeom3<N1, N2, W>;
+    constexpr int M = G::M, H = G::H, PL = G::PL, EL = G::EL;
+    __shared__ C2<float> tw[M];
+    __shared__ C2<float> E[3 * EL];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = blk % G::NG, y = blk / G::NG;
+    const int c = threadIdx.x / G::GT;
+    const int t = threadIdx.x - c * G::GT;
+    const int w = t % W, p = t / W;
+    static_assert((unsigned long long)3 * M * M * H * 8 < (1ull << 31), "offsets exceed 31 bits");
+    constexpr int cstride = M * M * H * 8, zstride = M * H * 8;
+    C2<float>* base = spec + (size_t)y * H + g * W;
+    const int nbytes = (int)(((size_t)3 * M * M * H - ((size_t)y * H + g * W)) * 8);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nbytes, kBufferWord3);
+    const int lo = c * cstride + p * zstride + w * 8;
+    for (int e = threadIdx.x; e < M; e += G::NT) tw[e] = twg[e];
+    C2<float> v[N1];
+#pragma unroll
+    for (int j = 0; j < N1; ++j) v[j] = buf_load(rs, lo, j * N2 * zstride);
+    __syncthreads();
+    C2<float>* Ec = E + c * EL + w;
+    four_step<N1, N2, -1, 1>(v, tw, Ec, p, PL, W);
+    // projection: u^ = (I - k k^T / k^2) f^ / (eta k^2 M^3); k = 0 and index-H modes -> 0.
+    // The coefficients go to LDS and every thread projects elements of the
+    // tile, all three components at a time; the lines' registers are free
+    // meanwhile.
+#pragma unroll
+    for (int i = 0; i < N1; ++i) Ec[i * PL + p * W] = v[i];
+    __syncthreads();
+    const float kux = (float)pa.kux, kuy = (float)pa.kuy, kuz = (float)pa.kuz, sc = (float)pa.scale;
+    const int jy = y < H ? y : y - M;
+    const float ky = kuy * (float)jy;
+    constexpr int LW = N2 * W;   // elements of one k1 row of the tile
+#pragma unroll 2
+    for (int e = threadIdx.x; e < N1 * LW; e += G::NT) {
+        const int i = e / LW, r = e - i * LW;
+        const int pp = r / W, ww = r - pp * W;
+        const int o = i * PL + pp * W + ww;
+        const int jx = g * W + ww;
+        const int iz = pp + N2 * i;
+        const int jz = iz < H ? iz : iz - M;
+        const bool zero = (y == H) || (iz == H) || (jx == 0 && jy == 0 && jz == 0);
+        const float kx = kux * (float)jx, kz = kuz * (float)jz;
+        const float k2s = kx * kx + ky * ky + kz * kz;
+        const float ik2 = zero ? 0.0f : 1.0f / k2s;
+        const C2<float> f0 = E[o], f1 = E[EL + o], f2 = E[2 * EL + o];
+        const C2<float> kf = {(kx * f0.x + ky * f1.x + kz * f2.x) * ik2,
+                              (kx * f0.y + ky * f1.y + kz * f2.y) * ik2};
+        const float s = pa.root ? sc * sqrtf(ik2) : sc * ik2;
+        E[o] = C2<float>{(f0.x - kx * kf.x) * s, (f0.y - kx * kf.y) * s};
+        E[EL + o] = C2<float>{(f1.x - ky * kf.x) * s, (f1.y - ky * kf.y) * s};
+        E[2 * EL + o] = C2<float>{(f2.x - kz * kf.x) * s, (f2.y - kz * kf.y) * s};
+    }
+    __syncthreads();
+    // each thread reads back the slots its own exchange writes next: no barrier
+#pragma unroll
+    for (int i = 0; i < N1; ++i) v[i] = Ec[i * PL + p * W];
+    four_step<N1, N2, 1, 1>(v, tw, Ec, p, PL, W);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) buf_store(v[i], rs, lo, i * N2 * zstride);
+}
+
+// Four-step transform of length N = N1 N2 for any N1, N2 (N2 need not divide
+// N1): a line has LT = max(N1, N2) threads t.  In: threads t < N2 hold
+// r[j] = x[t + N2 j], j < N1; they do the N1-point DFTs and twiddle by
+// exp(-+2 pi i t k1 / N), then threads t < N1 take the N2 values of k1 = t
+// through LDS and do the N2-point DFTs.  Out: threads t < N1 hold
+// r[k2] = X[t + N1 k2], k2 < N2.  E: element (k1, a) at E[k1 ES + a EP].
+template <int N1, int N2, int DIR>
+__device__ inline void four_step_split(C2<float>* r, const C2<float>* tw, C2<float>* E, int t, int ES,
+                                       int EP) {
+    if (t < N2) {
+        RDFT<float, N1, DIR>::run(r);
+#pragma unroll
+        for (int k1 = 1; k1 < N1; ++k1) {
+            C2<float> f = tw[t * k1];
+            if (DIR > 0) f.y = -f.y;
+            r[k1] = cmul(r[k1], f);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) E[k1 * ES + t * EP] = r[k1];
+    }
+    __syncthreads();
+    if (t < N1) {
+#pragma unroll
+        for (int a = 0; a < N2; ++a) r[a] = E[t * ES + a * EP];
+        RDFT<float, N2, DIR>::run(r);
+    }
+    __syncthreads();
+}
+
+// z pass with one thread group per component, each line split N = N1 N2 as
+// in four_step_split (W kx columns at one ky; 3 W max(N1, N2) threads).  The
+// forward coefficients go to a tile in LDS in natural z order, the projection
+// runs on the tile with the arithmetic of k_fft_z_solve_reg, and each thread
+// reads back the input layout of the (inverse) split transform.
+template <int N1, int N2, int W>
+struct ZGeomSplit {
+    static constexpr int M = N1 * N2;
+    static constexpr int H = M / 2;
+    static constexpr int LT = N1 > N2 ? N1 : N2;   // threads per line
+    static constexpr int GT = W * LT;               // threads per component group
+    static constexpr int NT = 3 * GT;               // threads per block
+    static constexpr int ES = N2 * W + 8;           // exchange: k1 stride (complex)
+    static constexpr int EC = (N1 * ES > M * W ? N1 * ES : M * W);   // one component's LDS
+    static constexpr int NG = H / W;
+    static_assert(H % W == 0, "W must divide M/2");
+    static_assert(NT <= 1024, "block size");
+};
+
+template <int N1, int N2, int W>
+__global__ __launch_bounds__(3 * W * (N1 > N2 ? N1 : N2)) void k_fft_z_solve_split(
+    C2<float>* __restrict__ spec, const C2<float>* __restrict__ twg, ProjArgs pa) {
+    using G = ZGeomSplit<N1, N2, W>;
+    constexpr int M = G::M, H = G::H, LT = G::LT, ES = G::ES, EC = G::EC;
+    __shared__ C2<float> tw[M];
+    __shared__ C2<float> E[3 * EC];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = blk % G::NG, y = blk / G::NG;
+    const int c = threadIdx.x / G::GT;
+    const int tt = threadIdx.x - c * G::GT;
+    const int w = tt % W, t = tt / W;
+    static_assert((unsigned long long)3 * M * M * H * 8 < (1ull << 31), "offsets exceed 31 bits");
+    constexpr int cstride = M * M * H * 8, zstride = M * H * 8;
+    C2<float>* base = spec + (size_t)y * H + g * W;
+    const int nbytes = (int)(((size_t)3 * M * M * H - ((size_t)y * H + g * W)) * 8);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nbytes, kBufferWord3);
+    const int lo = c * cstride + t * zstride + w * 8;
+    for (int e = threadIdx.x; e < M; e += G::NT) tw[e] = twg[e];
+    C2<float> r[LT];
+    if (t < N2) {
+#pragma unroll
+        for (int j = 0; j < N1; ++j) r[j] = buf_load(rs, lo, j * N2 * zstride);
+    }
+    __syncthreads();
+    C2<float>* Ec = E + c * EC + w;
+    four_step_split<N1, N2, -1>(r, tw, Ec, t, ES, W);
+    // the coefficients in natural z order: (z, column) at Ec[z W]
+    if (t < N1) {
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) Ec[(t + N1 * k2) * W] = r[k2];
+    }
+    __syncthreads();
+    // projection: u^ = (I - k k^T / k^2) f^ / (eta k^2 M^3); k = 0 and index-H modes -> 0
+    const float kux = (float)pa.kux, kuy = (float)pa.kuy, kuz = (float)pa.kuz, sc = (float)pa.scale;
+    const int jy = y < H ? y : y - M;
+    const float ky = kuy * (float)jy;
+#pragma unroll 2
+    for (int e = threadIdx.x; e < M * W; e += G::NT) {
+        const int iz = e / W, ww = e - iz * W;
+        const int jx = g * W + ww;
+        const int jz = iz < H ? iz : iz - M;
+        const bool zero = (y == H) || (iz == H) || (jx == 0 && jy == 0 && jz == 0);
+        const float kx = kux * (float)jx, kz = kuz * (float)jz;
+        const float k2s = kx * kx + ky * ky + kz * kz;
+        const float ik2 = zero ? 0.0f : 1.0f / k2s;
+        const C2<float> f0 = E[e], f1 = E[EC + e], f2 = E[2 * EC + e];
+        const C2<float> kf = {(kx * f0.x + ky * f1.x + kz * f2.x) * ik2,
+                              (kx * f0.y + ky * f1.y + kz * f2.y) * ik2};
+        const float s = pa.root ? sc * sqrtf(ik2) : sc * ik2;
+        E[e] = C2<float>{(f0.x - kx * kf.x) * s, (f0.y - kx * kf.y) * s};
+        E[EC + e] = C2<float>{(f1.x - ky * kf.x) * s, (f1.y - ky * kf.y) * s};
+        E[2 * EC + e] = C2<float>{(f2.x - kz * kf.x) * s, (f2.y - kz * kf.y) * s};
+    }
+    __syncthreads();
+    if (t < N2) {
+#pragma unroll
+        for (int j = 0; j < N1; ++j) r[j] = Ec[(t + N2 * j) * W];
+    }
+    __syncthreads();
+    four_step_split<N1, N2, 1>(r, tw, Ec, t, ES, W);
+    if (t < N1) {
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) buf_store(r[k2], rs, lo, k2 * N1 * zstride);
+    }
+}
+
 // x passes for a half-length H = N1 N2: T = N2 threads per line hold the
 // values of index congruent to their lane q modulo T, before and after the
 // transform.  The real/complex split pairs index k with H - k, whose holder
@@ -935,8 +1133,11 @@ ProjArgs proj_args(const fcm_plan_impl* P, bool root) {
     return pa;
 }
 
+// how the z pass of a register size runs
+constexpr int kZLds = 0, kZReg = 1, kZGroups = 2, kZSplit = 3;
+
 // FP32 solve with register passes (RegPlan sizes)
-template <int XN1, int XN2, int YN1, int YN2, int YW, bool ZREG>
+template <int XN1, int XN2, int YN1, int YN2, int YW, int ZMODE, int ZW, int ZN1, int ZN2>
 hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEvent_t* ev, bool tiled,
                      bool root) {
     using X = XGeom<XN1, XN2>;
@@ -973,10 +1174,18 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
                            spec, tw);
     }
     mark(2);
-    if constexpr (ZREG)
+    if constexpr (ZMODE == kZReg)
         hipLaunchKernelGGL((k_fft_z_solve_reg<YN1, YN2, YW>), dim3(Y::NG * M), dim3(Y::NT), 0, st, spec,
                            tw, proj_args(P, root));
-    else
+    else if constexpr (ZMODE == kZGroups) {
+        using Z = ZGeom3<YN1, YN2, ZW>;
+        hipLaunchKernelGGL((k_fft_z_solve_3g<YN1, YN2, ZW>), dim3(Z::NG * M), dim3(Z::NT), 0, st, spec,
+                           tw, proj_args(P, root));
+    } else if constexpr (ZMODE == kZSplit) {
+        using Z = ZGeomSplit<ZN1, ZN2, ZW>;
+        hipLaunchKernelGGL((k_fft_z_solve_split<ZN1, ZN2, ZW>), dim3(Z::NG * M), dim3(Z::NT), 0, st,
+                           spec, tw, proj_args(P, root));
+    } else
         z_lds<float, 8>(P, spec, tw, st, proj_args(P, root));
     mark(3);
     if constexpr (fused) {
@@ -998,28 +1207,30 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     return hipGetLastError();
 }
 
-// The sizes with register passes: M -> (x: M/2 = XN1 XN2), (y, z: M = YN1 YN2 over
-// YW columns), whether the z pass runs in registers (at 324 it fits only at one
-// wavefront per SIMD, and the LDS pass is faster).
-#define FCM_REG_SIZES(X)                   \
-    X(64, 8, 4, 8, 8, 32, true)            \
-    X(72, 18, 2, 12, 6, 36, true)          \
-    X(96, 12, 4, 24, 4, 48, true)          \
-    X(108, 18, 3, 18, 6, 27, true)         \
-    X(128, 8, 8, 16, 8, 32, true)          \
-    X(144, 12, 6, 12, 12, 18, true)        \
-    X(162, 9, 9, 18, 9, 27, true)          \
-    X(192, 24, 4, 24, 8, 32, true)         \
-    X(216, 18, 6, 36, 6, 18, false)        \
-    X(256, 16, 8, 16, 16, 16, true)        \
-    X(288, 12, 12, 24, 12, 16, true)       \
-    X(324, 18, 9, 18, 18, 9, false)        \
-    X(384, 24, 8, 48, 8, 16, false)        \
-    X(432, 36, 6, 36, 12, 12, false)
+// The sizes with register passes: M -> (x: M/2 = XN1 XN2), (y: M = YN1 YN2 over
+// YW columns), how the z pass runs and over how many columns ZW (kZReg: three
+// components a thread over YW columns; kZGroups: one component a thread with
+// the y factorisation; kZSplit: one component a thread, M = ZN1 ZN2 split as
+// in four_step_split; kZLds: the LDS Stockham pass).
+#define FCM_REG_SIZES(X)                                 \
+    X(64, 8, 4, 8, 8, 32, kZReg, 0, 0, 0)                \
+    X(72, 18, 2, 12, 6, 36, kZReg, 0, 0, 0)              \
+    X(96, 12, 4, 24, 4, 48, kZReg, 0, 0, 0)              \
+    X(108, 18, 3, 18, 6, 27, kZReg, 0, 0, 0)             \
+    X(128, 8, 8, 16, 8, 32, kZReg, 0, 0, 0)              \
+    X(144, 12, 6, 12, 12, 18, kZReg, 0, 0, 0)            \
+    X(162, 9, 9, 18, 9, 27, kZReg, 0, 0, 0)              \
+    X(192, 24, 4, 24, 8, 32, kZReg, 0, 0, 0)             \
+    X(216, 18, 6, 36, 6, 18, kZSplit, 4, 18, 12)         \
+    X(256, 16, 8, 16, 16, 16, kZReg, 0, 0, 0)            \
+    X(288, 12, 12, 24, 12, 16, kZSplit, 4, 16, 18)       \
+    X(324, 18, 9, 18, 18, 9, kZGroups, 9, 0, 0)          \
+    X(384, 24, 8, 48, 8, 16, kZSplit, 8, 24, 16)         \
+    X(432, 36, 6, 36, 12, 12, kZGroups, 4, 0, 0)
 
 bool reg_size(int M) {
-#define FCM_REG_CASE(m, a, b, c, d, e, f) \
-    case m:                               \
+#define FCM_REG_CASE(m, a, b, c, d, e, f, g, h, i) \
+    case m:                                        \
         return true;
     switch (M) {
         FCM_REG_SIZES(FCM_REG_CASE)
@@ -1032,9 +1243,9 @@ template <typename R, int MX, int MZ>
 hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* ev, bool tiled,
                    bool root) {
     if constexpr (sizeof(R) == sizeof(float)) {
-#define FCM_REG_CASE(m, a, b, c, d, e, f) \
-    case m:                               \
-        return solve_reg<a, b, c, d, e, f>(P, grid, st, ev, tiled, root);
+#define FCM_REG_CASE(m, a, b, c, d, e, f, g, h, i) \
+    case m:                                        \
+        return solve_reg<a, b, c, d, e, f, g, h, i>(P, grid, st, ev, tiled, root);
         if (P->cubic) switch (P->M) {
                 FCM_REG_SIZES(FCM_REG_CASE)
                 default: break;
