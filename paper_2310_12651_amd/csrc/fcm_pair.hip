@@ -16,8 +16,9 @@
 // neighbours per thread.  The evaluation takes kPairPerBlock consecutive
 // particles per workgroup, queues their recorded pairs in LDS order and
 // evaluates them with all threads, so the FP64 body (erfc, exp) runs with
-// full wavefronts; a thread whose layer had more neighbours than fit rescans
-// it and evaluates the rest itself.
+// full wavefronts; threads whose layer had more neighbours than the scan
+// recorded rescan it for the next few and queue those for further passes of
+// the whole workgroup.
 //
 // The blocks, with xh = x/r and (-x cross) T = T x x:
 //   C_VF = Avf I + Bvf xh xh^T    (S(sigma sqrt2) - S~ - (sigma^2-Sigma^2) Q(Sigma sqrt2)
@@ -142,19 +143,15 @@ __device__ inline double4 min_image(double4 p, double4 o, const PairArgs& a) {
     return make_double4(x0, x1, x2, x0 * x0 + x1 * x1 + x2 * x2);
 }
 
-// Neighbours of particle j (position mp, cell `cell`) in the z layer `layer`
-// (0, 1, 2 = cz-1, cz, cz+1) within R_c, q != j: hit(q) for each, in a fixed
-// order.  Candidate positions are loaded four at a time.
-template <class Hit>
-__device__ inline void scan_layer(const double4* __restrict__ pos4, const int* __restrict__ cell_start,
-                                  const PairArgs& a, int j, double4 mp, int cell, int layer,
-                                  Hit&& hit) {
+// The candidates of particle j's z layer `layer` (0, 1, 2 = cz-1, cz, cz+1)
+// of the 3x3x3 cells around `cell`: x neighbours cx-1, cx, cx+1 (mod m) of
+// the three rows, one or two runs of cells each; run k is [rb[k], re[k]).
+__device__ inline void layer_runs(const int* __restrict__ cell_start, const PairArgs& a, int cell,
+                                  int layer, int* rb, int* re) {
     const int mx = a.mx, my = a.my, mz = a.mz;
     const int cx = cell % mx, cy = (cell / mx) % my, cz = cell / (mx * my);
     int nz = cz + layer - 1;
     nz = nz < 0 ? nz + mz : (nz >= mz ? nz - mz : nz);
-    // x neighbours cx-1, cx, cx+1 (mod m) of the three rows: one or two runs of cells
-    int rb[6], re[6];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         int ny = cy + r - 1;
@@ -177,6 +174,17 @@ __device__ inline void scan_layer(const double4* __restrict__ pos4, const int* _
             re[2 * r + 1] = 0;
         }
     }
+}
+
+// Neighbours of particle j (position mp, cell `cell`) in the z layer `layer`
+// within R_c, q != j: hit(q) for each, in a fixed order (runs in turn,
+// ascending q).  Candidate positions are loaded four at a time.
+template <class Hit>
+__device__ inline void scan_layer(const double4* __restrict__ pos4, const int* __restrict__ cell_start,
+                                  const PairArgs& a, int j, double4 mp, int cell, int layer,
+                                  Hit&& hit) {
+    int rb[6], re[6];
+    layer_runs(cell_start, a, cell, layer, rb, re);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const int b = rb[k], e = re[k];
@@ -194,6 +202,51 @@ __device__ inline void scan_layer(const double4* __restrict__ pos4, const int* _
             }
         }
     }
+}
+
+// The same scan, resumable: from candidate `pos` of run `run` (pos < 0: the
+// run's start), skip the first `skip` neighbours, then store the next ones in
+// out[] until `cap` are stored or the layer ends.  Returns the number stored;
+// (run, pos) then name the first candidate not yet examined.
+__device__ inline int scan_layer_resume(const double4* __restrict__ pos4,
+                                        const int* __restrict__ cell_start, const PairArgs& a, int j,
+                                        double4 mp, int cell, int layer, int& run, int& pos, int skip,
+                                        int cap, int* out) {
+    int rb[6], re[6];
+    layer_runs(cell_start, a, cell, layer, rb, re);
+    int got = 0;
+    for (; run < 6; ++run, pos = -1) {
+        const int e = re[run];
+        if (pos < 0) pos = rb[run];
+        for (; pos < e; pos += 4) {
+            double4 c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] = pos4[min(pos + u, e - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = pos + u;
+                if (q < e) {
+                    const double4 x = min_image(mp, c[u], a);
+                    if (q != j && x.w < a.rc2) {
+                        if (skip > 0) {
+                            --skip;
+                        } else {
+                            out[got++] = q;
+                            if (got == cap) {
+                                pos = q + 1;
+                                if (pos >= e) {
+                                    ++run;
+                                    pos = -1;
+                                }
+                                return got;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return got;
 }
 
 // thread t = 3 j + layer records the first kPairCap neighbours of particle j
@@ -215,6 +268,8 @@ __global__ __launch_bounds__(kScanBlock) void k_pair_scan(const double4* __restr
     count[t] = n;
 }
 
+constexpr int kRefill = 24;   // evaluation: hits a thread queues per refill pass (LDS)
+
 template <bool SAME>
 __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restrict__ pos4,
                                                           const PairRec* __restrict__ rec,
@@ -226,106 +281,102 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_eval(const double4* __restr
     __shared__ int qoff[kPairBlock + 1];         // queue offset of each thread's pairs
     __shared__ int wsum[kPairBlock / 64];
     __shared__ double res[kPairBlock][6];        // evaluated pairs of one round
+    __shared__ int rq[kPairBlock * kRefill];     // refill passes: each thread's next hits
     const int tid = threadIdx.x;
     const int base = xcd_remap(blockIdx.x, gridDim.x) * kPairPerBlock;
     const int pl = tid / 3, layer = tid - 3 * pl;  // local particle, z layer
     const int j = base + pl;
     const bool active = tid < kPairThreads && j < a.N;
     const size_t t0 = (size_t)3 * base;          // scan thread of local thread 0
-    const int ntrue = (active && a.with_pairs) ? count[t0 + tid] : 0;
-    const int nh = min(ntrue, kPairCap);
+    int ntrue = (active && a.with_pairs) ? count[t0 + tid] : 0;
 
-    // queue offsets: exclusive scan of the per-thread counts
-    {
-        const int lane = tid & 63, wid = tid >> 6;
-        int inc = nh;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int u = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += u;
-        }
-        if (lane == 63) wsum[wid] = inc;
-        __syncthreads();
-        int pre = 0;
-        for (int k = 0; k < wid; ++k) pre += wsum[k];
-        qoff[tid] = pre + inc - nh;
-        if (tid == kPairBlock - 1) qoff[kPairBlock] = pre + inc;
-        __syncthreads();
-    }
-    const int total = qoff[kPairBlock];
-
-    // evaluate the queue in rounds of kPairBlock pairs; the layer-0 thread of
-    // each particle adds its particle's results of the round in queue order
+    // Pass 0 evaluates the hits the scan recorded.  While a thread of the
+    // block has more, each such thread rescans its layer for its next kRefill
+    // hits into LDS and the block evaluates them in another pass, so long
+    // neighbour lists keep every thread busy.  A particle's pairs are summed
+    // pass by pass, layer by layer, in scan order.
+    int nq = min(ntrue, kPairCap);               // this pass's hits of this thread
+    int taken = 0;                               // hits consumed by earlier passes
+    int srun = 0, spos = -1;                     // where the refill scan resumes
     double v[3] = {0, 0, 0}, w[3] = {0, 0, 0};
-    for (int r0 = 0; r0 < total; r0 += kPairBlock) {
-        const int e = r0 + tid;
-        if (e < total) {
-            // the thread that recorded pair e: the last one whose offset is <= e
-            int lo = 0, hi = kPairBlock - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (qoff[mid] <= e) lo = mid;
-                else hi = mid - 1;
+    for (int pass = 0;; ++pass) {
+        // queue offsets: exclusive scan of the per-thread counts
+        {
+            const int lane = tid & 63, wid = tid >> 6;
+            int inc = nq;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += u;
             }
-            const int q = hits[(t0 + lo) * kPairCap + (e - qoff[lo])];
-            const double4 y = min_image(pos4[base + lo / 3], pos4[q], a);
-            double rv[3] = {0, 0, 0}, rw[3] = {0, 0, 0};
-            add_pair<SAME>(y.x, y.y, y.z, y.w, rec[q], a, rv, rw);
-            res[tid][0] = rv[0];
-            res[tid][1] = rv[1];
-            res[tid][2] = rv[2];
-            res[tid][3] = rw[0];
-            res[tid][4] = rw[1];
-            res[tid][5] = rw[2];
+            if (lane == 63) wsum[wid] = inc;
+            __syncthreads();
+            int pre = 0;
+            for (int k = 0; k < wid; ++k) pre += wsum[k];
+            qoff[tid] = pre + inc - nq;
+            if (tid == kPairBlock - 1) qoff[kPairBlock] = pre + inc;
+            __syncthreads();
         }
-        __syncthreads();
-        if (active && layer == 0) {
-            const int lo = max(qoff[tid], r0), hi = min(qoff[tid + 3], r0 + kPairBlock);
-            for (int k = lo; k < hi; ++k) {
-                const double* rr = res[k - r0];
-                v[0] += rr[0];
-                v[1] += rr[1];
-                v[2] += rr[2];
-                w[0] += rr[3];
-                w[1] += rr[4];
-                w[2] += rr[5];
+        const int total = qoff[kPairBlock];
+
+        // evaluate the queue in rounds of kPairBlock pairs; the layer-0 thread
+        // of each particle adds its particle's results of the round in queue order
+        for (int r0 = 0; r0 < total; r0 += kPairBlock) {
+            const int e = r0 + tid;
+            if (e < total) {
+                // the thread that queued pair e: the last one whose offset is <= e
+                int lo = 0, hi = kPairBlock - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (qoff[mid] <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int q = pass == 0 ? hits[(t0 + lo) * kPairCap + (e - qoff[lo])]
+                                        : rq[lo * kRefill + (e - qoff[lo])];
+                const double4 y = min_image(pos4[base + lo / 3], pos4[q], a);
+                double rv[3] = {0, 0, 0}, rw[3] = {0, 0, 0};
+                add_pair<SAME>(y.x, y.y, y.z, y.w, rec[q], a, rv, rw);
+                res[tid][0] = rv[0];
+                res[tid][1] = rv[1];
+                res[tid][2] = rv[2];
+                res[tid][3] = rw[0];
+                res[tid][4] = rw[1];
+                res[tid][5] = rw[2];
+            }
+            __syncthreads();
+            if (active && layer == 0) {
+                const int lo = max(qoff[tid], r0), hi = min(qoff[tid + 3], r0 + kPairBlock);
+                for (int k = lo; k < hi; ++k) {
+                    const double* rr = res[k - r0];
+                    v[0] += rr[0];
+                    v[1] += rr[1];
+                    v[2] += rr[2];
+                    w[0] += rr[3];
+                    w[1] += rr[4];
+                    w[2] += rr[5];
+                }
+            }
+            __syncthreads();
+        }
+
+        taken += nq;
+        const int rem = ntrue - taken;
+        if (!__syncthreads_or(rem > 0)) break;
+        nq = min(rem, kRefill);
+        if (nq > 0) {
+            // the first refill skips the hits the scan recorded; later ones resume
+            const int got = scan_layer_resume(pos4, cell_start, a, j, pos4[j], rec[j].cell, layer, srun,
+                                              spos, pass == 0 ? taken : 0, nq, rq + tid * kRefill);
+            // queue only what the rescan found (it repeats the scan's count)
+            if (got < nq) {
+                nq = got;
+                ntrue = taken + got;
             }
         }
-        __syncthreads();
     }
 
-    // neighbours beyond the recorded ones: rescan and evaluate them here
-    double pv[3] = {0, 0, 0}, pw[3] = {0, 0, 0};
-    if (ntrue > kPairCap) {
-        const double4 mp = pos4[j];
-        int k = 0;
-        scan_layer(pos4, cell_start, a, j, mp, rec[j].cell, layer, [&](int q) {
-            if (k++ >= kPairCap) {
-                const double4 y = min_image(mp, pos4[q], a);
-                add_pair<SAME>(y.x, y.y, y.z, y.w, rec[q], a, pv, pw);
-            }
-        });
-    }
-    if (active) {
-        res[tid][0] = pv[0];
-        res[tid][1] = pv[1];
-        res[tid][2] = pv[2];
-        res[tid][3] = pw[0];
-        res[tid][4] = pw[1];
-        res[tid][5] = pw[2];
-    }
-    __syncthreads();
     if (active && layer == 0) {
         const PairRec me = rec[j];
-#pragma unroll
-        for (int l = 0; l <= 2; ++l) {
-            v[0] += res[tid + l][0];
-            v[1] += res[tid + l][1];
-            v[2] += res[tid + l][2];
-            w[0] += res[tid + l][3];
-            w[1] += res[tid + l][4];
-            w[2] += res[tid + l][5];
-        }
         const int64_t n = me.orig;
         const double c[6] = {a.selfVF * me.F[0] + v[0], a.selfVF * me.F[1] + v[1],
                              a.selfVF * me.F[2] + v[2], a.selfOT * me.T[0] + w[0],

@@ -6,7 +6,8 @@ checked on its own (spread, Stokes solve, interpolation, correction) and the
 whole mobility end to end, on grids that span several tiles and ragged
 tilings (grid sizes with factors of 3, odd supports), wrapped positions,
 torques on and off, a separate torque width, standard FCM, a crowded box
-(R_c near L/2, many neighbours per particle), supports M_G = 15 and 16 on
+(R_c near L/2, many neighbours per particle; with a separate torque width,
+about 300 of them), supports M_G = 15 and 16 on
 grids whose FP32 mobility runs in the tiled layout (the packed interpolation's
 widest form), and N = 1.
 """
@@ -59,6 +60,15 @@ def _case(name):
         w = dict(N=N, L=L, a=A, eta=1.0, grid=36, Sigma=1.2, M_G=12, R_c=14.0,
                  Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
         return w, None
+    if name == "crowded700":
+        # ~300 neighbours per particle, ~100 per z layer of the 3 x 3 x 3
+        # cells: twice what the scan records, so the evaluation runs several
+        # refill passes (each queues up to 12 more hits of a layer)
+        L, N = 30.0, 700
+        Y = workloads.rsa_positions(N, L, A, rng)
+        w = dict(N=N, L=L, a=A, eta=1.0, grid=36, Sigma=1.2, M_G=12, R_c=14.0,
+                 Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+        return w, 1.4
     if name == "tiny16":
         # grid narrower than support + tile (16 < 12 + 8): supports meet a
         # spreading tile on both sides of the periodic seam
@@ -106,7 +116,7 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["small", "ragged54", "wideTorque36", "standard48", "crowded", "tiny16", "support16",
+CASES = ["small", "ragged54", "wideTorque36", "standard48", "crowded", "crowded700", "tiny16", "support16",
          "support15", "support14", "single64", "single"]
 PREC = {"fp64": (0, 1e-10), "fp32": (1, 1e-5)}
 
