@@ -802,6 +802,53 @@ __global__ __launch_bounds__(3 * W * (N1 > N2 ? N1 : N2)) void k_fft_z_solve_spl
     }
 }
 
+// z pass of a box with a short z axis (MZ points): one (kx, ky) column a
+// thread, the three components' lines in registers (forward DFT, the
+// projection, inverse DFT); consecutive threads take consecutive kx, so every
+// load and store of a wavefront is one contiguous run.
+template <int MZ>
+__global__ __launch_bounds__(256) void k_fft_z_solve_col(C2<float>* __restrict__ spec, int H, int My,
+                                                         ProjArgs pa) {
+    const int t = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (t >= H * My) return;
+    const int jx = t % H, y = t / H;
+    const size_t zs = (size_t)My * H, cs = (size_t)MZ * zs;
+    C2<float>* col = spec + t;
+    C2<float> v[3][MZ];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int z = 0; z < MZ; ++z) v[c][z] = col[c * cs + z * zs];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) RDFT<float, MZ, -1>::run(v[c]);
+    // projection: u^ = (I - k k^T / k^2) f^ / (eta k^2 Mx My Mz); k = 0 and index-H modes -> 0
+    const float kux = (float)pa.kux, kuy = (float)pa.kuy, kuz = (float)pa.kuz, sc = (float)pa.scale;
+    const int Hy = My / 2;
+    const int jy = y < Hy ? y : y - My;
+    const float kx = kux * (float)jx, ky = kuy * (float)jy;
+#pragma unroll
+    for (int z = 0; z < MZ; ++z) {
+        const int jz = z < MZ / 2 ? z : z - MZ;
+        const bool zero = (y == Hy) || (z == MZ / 2) || (jx == 0 && jy == 0 && jz == 0);
+        const float kz = kuz * (float)jz;
+        const float k2s = kx * kx + ky * ky + kz * kz;
+        const float ik2 = zero ? 0.0f : 1.0f / k2s;
+        const C2<float> f0 = v[0][z], f1 = v[1][z], f2 = v[2][z];
+        const C2<float> kf = {(kx * f0.x + ky * f1.x + kz * f2.x) * ik2,
+                              (kx * f0.y + ky * f1.y + kz * f2.y) * ik2};
+        const float s = pa.root ? sc * sqrtf(ik2) : sc * ik2;
+        v[0][z] = C2<float>{(f0.x - kx * kf.x) * s, (f0.y - kx * kf.y) * s};
+        v[1][z] = C2<float>{(f1.x - ky * kf.x) * s, (f1.y - ky * kf.y) * s};
+        v[2][z] = C2<float>{(f2.x - kz * kf.x) * s, (f2.y - kz * kf.y) * s};
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) RDFT<float, MZ, 1>::run(v[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int z = 0; z < MZ; ++z) col[c * cs + z * zs] = v[c][z];
+}
+
 // x passes for a half-length H = N1 N2: T = N2 threads per line hold the
 // values of index congruent to their lane q modulo T, before and after the
 // transform.  The real/complex split pairs index k with H - k, whose holder
@@ -1207,6 +1254,74 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     return hipGetLastError();
 }
 
+// FP32 boxes with a square cross-section (Mx = My = M, a register size or
+// 512) and a short z axis (4, 8, 12 or 16 points): the register x and y
+// passes of M (fused where they fuse), in the row-major layout, around the
+// one-column-a-thread z pass.
+template <int MZ>
+void z_col(const fcm_plan_impl* P, C2<float>* spec, hipStream_t st, ProjArgs pa) {
+    const int H = P->H, My = P->My;
+    hipLaunchKernelGGL((k_fft_z_solve_col<MZ>), dim3((H * My + 255) / 256), dim3(256), 0, st, spec, H, My,
+                       pa);
+}
+
+bool box_zcol(int Mz) { return Mz == 4 || Mz == 8 || Mz == 12 || Mz == 16; }
+
+template <int XN1, int XN2, int YN1, int YN2, int YW>
+hipError_t solve_box(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEvent_t* ev, bool root) {
+    using X = XGeom<XN1, XN2>;
+    using Y = ColGeom<YN1, YN2, YW>;
+    static_assert(2 * X::H == Y::M, "x and y factorisations of the same M");
+    auto mark = [&](int i) {
+        if (ev && timing_event(P, i + 2)) (void)hipEventRecord(ev[i], st);
+    };
+    constexpr int M = Y::M;
+    const int Mz = P->Mz;
+    const C2<float>* tw = (const C2<float>*)P->twid;   // Mx = My: the x and y tables agree
+    C2<float>* spec = (C2<float>*)grid;
+    const int nlines = 3 * M * Mz;
+    const dim3 gx((nlines + X::LPB - 1) / X::LPB), bx(X::NT);
+    constexpr int FNT = fused_xy_threads(M);
+    using XY = XYGeom<M, XN1, XN2, YN1, YN2, (FNT > 0 ? FNT : 2 * M)>;
+    // the fused passes take one workgroup a plane: with fewer planes than
+    // CUs the separate passes spread wider
+    const bool fused = FNT > 0 && 3 * Mz >= 256;
+    const ProjArgs pa = proj_args(P, root);
+    mark(0);
+    if constexpr (FNT > 0) {
+        if (fused) hipLaunchKernelGGL((k_fft_xy_r2c<XY, false>), dim3(3 * Mz), dim3(FNT), 0, st, grid, tw);
+    }
+    if (!fused) {
+        hipLaunchKernelGGL((k_fft_x_r2c_reg<XN1, XN2, false>), gx, bx, 0, st, grid, tw, nlines);
+        mark(1);
+        hipLaunchKernelGGL((k_fft_y_reg<YN1, YN2, YW, -1>), dim3(Y::NG * 3 * Mz), dim3(Y::NT), 0, st,
+                           spec, tw);
+    } else {
+        mark(1);
+    }
+    mark(2);
+    switch (Mz) {
+        case 4: z_col<4>(P, spec, st, pa); break;
+        case 8: z_col<8>(P, spec, st, pa); break;
+        case 12: z_col<12>(P, spec, st, pa); break;
+        default: z_col<16>(P, spec, st, pa); break;
+    }
+    mark(3);
+    if (!fused) {
+        hipLaunchKernelGGL((k_fft_y_reg<YN1, YN2, YW, 1>), dim3(Y::NG * 3 * Mz), dim3(Y::NT), 0, st,
+                           spec, tw);
+        mark(4);
+        hipLaunchKernelGGL((k_fft_x_c2r_reg<XN1, XN2, false>), gx, bx, 0, st, grid, tw, nlines);
+    } else {
+        mark(4);
+    }
+    if constexpr (FNT > 0) {
+        if (fused) hipLaunchKernelGGL((k_fft_xy_c2r<XY, false>), dim3(3 * Mz), dim3(FNT), 0, st, grid, tw);
+    }
+    mark(5);
+    return hipGetLastError();
+}
+
 // The sizes with register passes: M -> (x: M/2 = XN1 XN2), (y: M = YN1 YN2 over
 // YW columns), how the z pass runs and over how many columns ZW (kZReg: three
 // components a thread over YW columns; kZGroups: one component a thread with
@@ -1251,6 +1366,15 @@ hipError_t solve_r(const fcm_plan_impl* P, R* grid, hipStream_t st, hipEvent_t* 
                 default: break;
             }
 #undef FCM_REG_CASE
+#define FCM_BOX_CASE(m, a, b, c, d, e, f, g, h, i) \
+    case m:                                        \
+        return solve_box<a, b, c, d, e>(P, grid, st, ev, root);
+        if (!P->cubic && P->M == P->My && box_zcol(P->Mz)) switch (P->M) {
+                FCM_REG_SIZES(FCM_BOX_CASE)
+                case 512: return solve_box<16, 16, 32, 16, 8>(P, grid, st, ev, root);
+                default: break;
+            }
+#undef FCM_BOX_CASE
     }
     auto mark = [&](int i) {
         if (ev && timing_event(P, i + 2)) (void)hipEventRecord(ev[i], st);
