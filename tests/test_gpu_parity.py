@@ -7,7 +7,8 @@ whole mobility end to end, on grids that span several tiles and ragged
 tilings (grid sizes with factors of 3, odd supports), wrapped positions,
 torques on and off, a separate torque width, standard FCM, a crowded box
 (R_c near L/2, many neighbours per particle; with a separate torque width,
-about 300 of them), supports M_G = 15 and 16 on
+about 300 of them), a dense cluster (spreading tiles with ~1500 candidates),
+supports M_G = 15 and 16 on
 grids whose FP32 mobility runs in the tiled layout (the packed interpolation's
 widest form), and N = 1.
 """
@@ -69,6 +70,17 @@ def _case(name):
         w = dict(N=N, L=L, a=A, eta=1.0, grid=36, Sigma=1.2, M_G=12, R_c=14.0,
                  Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
         return w, 1.4
+    if name == "cluster64":
+        # 1500 spheres packed in a 6^3 corner region (centres may overlap)
+        # and 200 spread over the box: the spreading tiles over the cluster
+        # hold ~1500 candidates each (a few tens elsewhere), and the pair
+        # search there finds ~800 neighbours a particle (refill passes)
+        L, N = 32.0, 1700
+        Y = np.concatenate([12.0 + rng.uniform(0.0, 6.0, size=(1500, 3)),
+                            rng.uniform(0.0, L, size=(200, 3))])
+        w = dict(N=N, L=L, a=A, eta=1.0, grid=64, Sigma=0.75, M_G=12, R_c=3.0,
+                 Y=Y, F=rng.normal(size=(N, 3)), T=rng.normal(size=(N, 3)))
+        return w, None
     if name == "tiny16":
         # grid narrower than support + tile (16 < 12 + 8): supports meet a
         # spreading tile on both sides of the periodic seam
@@ -116,7 +128,8 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["small", "ragged54", "wideTorque36", "standard48", "crowded", "crowded700", "tiny16", "support16",
+CASES = ["small", "ragged54", "wideTorque36", "standard48", "crowded", "crowded700", "cluster64", "tiny16",
+         "support16",
          "support15", "support14", "single64", "single"]
 PREC = {"fp64": (0, 1e-10), "fp32": (1, 1e-5)}
 
