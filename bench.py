@@ -62,6 +62,9 @@ def parse():
                          "a/L = 1/400 for the volume fractions of Table 3 (its optimum on this GPU)")
     ap.add_argument("--paper-grids", action="store_true",
                     help="call times on the grids of the paper's Sec. 6.3 runs (512x512x8, 256x256x16)")
+    ap.add_argument("--serving-grids", action="store_true",
+                    help="call and stage times (FP32 bulk) of the serving stream's largest "
+                         "request on each grid of 216^3 and above")
     ap.add_argument("--brownian", action="store_true",
                     help="instead of the headline run: time fcm_brownian on the workload (FP32 bulk "
                          "and FP64, Lanczos tolerance 1e-6)")
@@ -637,6 +640,49 @@ def paper_grids(args, torch):
     return out
 
 
+def serving_grids(args, torch):
+    """Call and per-stage times (FP32 bulk, one plan, warm) of the largest
+    request of the 512-request serving stream on each grid of 216^3 and above
+    (M_G = 16, Sigma from Table 3, R_c = 5.5 Sigma): the requests that set the
+    stream's p99."""
+    import workloads
+    from paper_2310_12651_amd import FCM_FP32_BULK, Plan
+    reqs = workloads.serving_stream(512)
+    big = {}
+    for r in reqs:
+        if r["grid"] >= 216 and (r["grid"] not in big or r["N"] > big[r["grid"]]["N"]):
+            big[r["grid"]] = r
+    dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    out = []
+    for g in sorted(big):
+        r = big[g]
+        Y, F, T = (dev(x) for x in workloads.request_inputs(r))
+        V = torch.empty((r["N"], 3), dtype=torch.float64, device="cuda")
+        W = torch.empty_like(V)
+        plan = Plan(r["N"], r["L"], r["a"], r["Sigma"], g, r["R_c"], support=r["M_G"], precision=FCM_FP32_BULK)
+        for _ in range(3):
+            plan.mobility(Y, F, T, V, W)
+        plan.set_timing(True)
+        for _ in range(5):
+            plan.mobility(Y, F, T, V, W)
+        stages, nc = plan.stage_times()
+        plan.set_timing(False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            plan.mobility(Y, F, T, V, W)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out.append({"grid": g, "request": r["id"], "N": r["N"], "phi": round(r["phi"], 4),
+                    "ms_per_call": round(ms, 4),
+                    "stages_ms": {k: round(v / max(nc, 1), 4) for k, v in stages.items()}})
+        log(f"[bench] serving grid {g}^3 request {r['id']} N={r['N']}: {ms:.3f} ms")
+        plan.close()
+    return {"serving_grids": out}
+
+
 def brownian_leg(args, torch):
     """Brownian velocities (fcm_brownian) on the workload: ms per call for FP32
     bulk and FP64 with seeded noise (grid noise in the grid precision), the
@@ -698,6 +744,9 @@ def main():
         return
     if args.paper_grids:
         print(json.dumps(paper_grids(args, torch)), flush=True)
+        return
+    if args.serving_grids:
+        print(json.dumps(serving_grids(args, torch)), flush=True)
         return
     if args.tune_sigma:
         print(json.dumps(tune_sigma(args, torch)), flush=True)
