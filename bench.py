@@ -80,7 +80,7 @@ def log(*a):
 
 # FP32 grids whose x and y passes run as one kernel per (component, z) plane:
 # the x stage times the fused pass and the y stage is empty
-FUSED_XY_GRIDS = (64, 96, 128, 256)
+FUSED_XY_GRIDS = (64, 96, 128, 192, 256)
 
 
 def algorithmic_bytes(w, stage):

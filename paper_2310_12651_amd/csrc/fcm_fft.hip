@@ -1034,7 +1034,7 @@ struct XYGeom {
 
 // threads of the fused passes for an M x M plane (0: separate passes)
 constexpr int fused_xy_threads(int M) {
-    return M == 64 ? 256 : M == 96 ? 192 : M == 128 ? 512 : M == 256 ? 1024 : 0;
+    return M == 64 ? 256 : M == 96 ? 192 : M == 128 ? 512 : M == 192 ? 384 : M == 256 ? 1024 : 0;
 }
 
 // element x (even) of line y of a plane: its pair of reals (x, x + 1)
