@@ -29,9 +29,17 @@ from . import closed_forms as cf
 from .fastfcm import interp, min_image, wrap
 
 
-def grid_sqrt_solve(p, xi):
-    """G^(1/2) xi on the grid: xi and the result have shape (3, Mx, My, Mz)."""
-    fh = np.fft.fftn(np.asarray(xi, dtype=np.float64), axes=(1, 2, 3))
+def grid_sqrt_solve(p, xi, workers=None):
+    """G^(1/2) xi on the grid: xi and the result have shape (3, Mx, My, Mz).
+    ``workers``: None uses numpy's FFT (one thread); a number uses scipy's FFT
+    with that many threads (the same transform, for the largest grids)."""
+    if workers is None:
+        fftn, ifftn = np.fft.fftn, np.fft.ifftn
+    else:
+        import scipy.fft as sfft
+        fftn = lambda a, axes: sfft.fftn(a, axes=axes, workers=workers)
+        ifftn = lambda a, axes: sfft.ifftn(a, axes=axes, workers=workers)
+    fh = fftn(np.asarray(xi, dtype=np.float64), axes=(1, 2, 3))
     Mx, My, Mz = p.Mv
     kx = (2.0 * np.pi * np.fft.fftfreq(Mx, d=1.0 / Mx) / p.Lv[0])[:, None, None]
     ky = (2.0 * np.pi * np.fft.fftfreq(My, d=1.0 / My) / p.Lv[1])[None, :, None]
@@ -51,12 +59,12 @@ def grid_sqrt_solve(p, xi):
         uh[:, :, My // 2, :] = 0.0
     if Mz % 2 == 0:
         uh[:, :, :, Mz // 2] = 0.0
-    return np.real(np.fft.ifftn(uh, axes=(1, 2, 3)))
+    return np.real(ifftn(uh, axes=(1, 2, 3)))
 
 
-def brownian_grid(p, Y, xi, kT):
+def brownian_grid(p, Y, xi, kT, workers=None):
     """sqrt(2 kT / dV) J~[G^(1/2) xi] at the particles (N x 3)."""
-    V, _ = interp(p, Y, grid_sqrt_solve(p, xi), want_omega=False)
+    V, _ = interp(p, Y, grid_sqrt_solve(p, xi, workers), want_omega=False)
     return np.sqrt(2.0 * kT / p.dx ** 3) * V
 
 

@@ -68,3 +68,32 @@ def test_brownian_in_a_rectangular_box():
     plan = Plan(N, L, A, 0.75, M, 5.9, support=14, precision=0)
     V, _ = plan.brownian(dev(Y), _grid_tensor(plan, xg), dev(xp), 2.0, tol=1e-12)
     assert normwise(host(V), br.brownian(p, Y, xg, xp, 2.0)) < 1e-9
+
+
+@pytest.mark.parametrize("M", [(216,) * 3, (288,) * 3, (324,) * 3, (64, 64, 16), (32, 32, 8)],
+                         ids=lambda M: "x".join(map(str, M)))
+def test_brownian_grid_part_fp32_register_z_passes(M):
+    """The grid part in FP32 on grids whose z pass takes one component per
+    thread group (216^3 and 288^3 with the split line, 324^3 with the four-step
+    of the y pass) or one column per thread (square boxes with 16 and 8 z
+    points), where the projection takes the square root of the Stokes
+    multiplier: standard FCM (no pair part) against the oracle on the same
+    noise.  The oracle's FFT runs on scipy threads at these sizes."""
+    import os
+
+    from paper_2310_12651_amd import FCM_FP32_BULK, Plan
+    N, kT = 40, 0.7
+    L = tuple(m * SIG for m in M)
+    rng = np.random.default_rng(sum(M))
+    Y = rng.uniform(0.0, 1.0, size=(N, 3)) * np.array(L)
+    p = ff.Params(L=L, M=M, a=A, Sigma=SIG, M_G=10, R_c=0.0, Sigma_D=SIGD)
+    xg = rng.normal(size=(3,) + tuple(M))
+    plan = Plan(N, L, A, SIG, M, 0.0, support=10, precision=FCM_FP32_BULK, sigma_D_grid=SIGD)
+    try:
+        V, it = plan.brownian(dev(Y), _grid_tensor(plan, xg), None, kT)
+        Vh = host(V)
+    finally:
+        plan.close()
+    assert it == 0
+    ref = br.brownian_grid(p, Y, xg, kT, workers=min(16, os.cpu_count() or 1))
+    assert normwise(Vh, ref) < 1e-5, (M, normwise(Vh, ref))
