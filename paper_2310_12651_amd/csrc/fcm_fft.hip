@@ -899,12 +899,70 @@ __device__ inline void x_partners(const C2<float>* v, C2<float>* pv, C2<float>* 
     }
 }
 
+// Moves a block's LPB lines between HBM and its line buffers in LDS (line ll
+// at E + ll LS, complex index k).  The lines of a block are the floats
+// [line0 M, (line0 + LPB) M) of the grid in either layout (LPB and M are
+// multiples of 4, so a block holds whole tile rows), so the block reads or
+// writes them as one contiguous run of 16-byte vectors; nf of those floats
+// belong to lines that exist.  TILED: tiles of 8 x by 4 y; otherwise line
+// after line (the row-major real grid, or the spectrum's H complex a line).
+// A 16-byte vector must not straddle two lines: M a multiple of 4.
+template <int M, int LPB, int LS, int NT, bool TILED, bool LOAD>
+__device__ inline void stage_lines(float* __restrict__ blk, C2<float>* E, int nf) {
+    static_assert(M % 4 == 0 && LPB % 4 == 0, "whole vectors and tile rows a block");
+    // every vector of the thread in flight at once (loads issued before any
+    // LDS write, LDS reads before any store)
+    constexpr int NV = (LPB * M / 4 + NT - 1) / NT;
+    float4 buf[NV];
+    const int f0 = 4 * (int)threadIdx.x;
+    if (LOAD) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int f = f0 + 4 * NT * i;
+            if (f < nf) buf[i] = *reinterpret_cast<const float4*>(blk + f);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int f = f0 + 4 * NT * i;
+        if (f >= nf) continue;
+        int ll, k;
+        if (TILED) {
+            const int r = f / (4 * M), rem = f - r * (4 * M);
+            ll = 4 * r + ((rem >> 3) & 3);
+            k = (((rem >> 5) << 3) + (rem & 7)) >> 1;
+        } else {
+            ll = f / M;
+            k = (f - ll * M) >> 1;
+        }
+        C2<float>* d = E + ll * LS + k;
+        if (LOAD) {
+            d[0] = C2<float>{buf[i].x, buf[i].y};
+            d[1] = C2<float>{buf[i].z, buf[i].w};
+        } else {
+            buf[i] = make_float4(d[0].x, d[0].y, d[1].x, d[1].y);
+        }
+    }
+    if (!LOAD) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int f = f0 + 4 * NT * i;
+            if (f < nf) *reinterpret_cast<float4*>(blk + f) = buf[i];
+        }
+    }
+}
+
 template <int N1, int N2, bool TILED>
 __global__ __launch_bounds__((XGeom<N1, N2>::NT)) void k_fft_x_r2c_reg(float* __restrict__ grid,
                                                                      const C2<float>* __restrict__ twg,
                                                                      int nlines) {
     using G = XGeom<N1, N2>;
     constexpr int H = G::H, T = G::T;
+    // The block's lines cross HBM as one contiguous run of 16-byte vectors,
+    // staged through the line buffers, where such vectors tile a line (H
+    // even); the output too where the registers allow (measured: faster for
+    // N1 <= 18, slower for N1 = 24, 36).
+    constexpr bool kStageIn = H % 2 == 0, kStageOut = kStageIn && N1 <= 18;
     __shared__ C2<float> tw[G::M];
     __shared__ C2<float> E[G::LPB * G::LS];
     const int tid = threadIdx.x, q = tid % T, ll = tid / T;
@@ -913,7 +971,15 @@ __global__ __launch_bounds__((XGeom<N1, N2>::NT)) void k_fft_x_r2c_reg(float* __
     C2<float>* g = reinterpret_cast<C2<float>*>(grid) + (size_t)(ok ? line : 0) * H;
     for (int e = tid; e < G::M; e += G::NT) tw[e] = twg[e];
     C2<float> v[N1];
-    if (TILED) {
+    const int line0 = line - ll;
+    float* blk = grid + (size_t)line0 * G::M;
+    const int nf = (min(nlines - line0, G::LPB)) * G::M;
+    if constexpr (kStageIn) {
+        stage_lines<G::M, G::LPB, G::LS, G::NT, TILED, true>(blk, E, nf);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < N1; ++j) v[j] = E[ll * G::LS + j * T + q];
+    } else if (TILED) {
         // tiles of 8 x by 4 y (as written by the spread); a block's lines are
         // groups of 4 consecutive y
         constexpr int M = G::M;
@@ -942,7 +1008,15 @@ __global__ __launch_bounds__((XGeom<N1, N2>::NT)) void k_fft_x_r2c_reg(float* __
         const int k = q + T * i;
         const C2<float> S = cadd(v[i], Zc), D = csub(v[i], Zc);
         const C2<float> WD = cmul(tw[k], D);
-        if (ok) g[k] = C2<float>{0.5f * (S.x + WD.y), 0.5f * (S.y - WD.x)};
+        const C2<float> X = {0.5f * (S.x + WD.y), 0.5f * (S.y - WD.x)};
+        if constexpr (kStageOut)
+            E[ll * G::LS + k] = X;
+        else if (ok)
+            g[k] = X;
+    }
+    if constexpr (kStageOut) {
+        __syncthreads();
+        stage_lines<G::M, G::LPB, G::LS, G::NT, false, false>(blk, E, nf);
     }
 }
 
@@ -1340,7 +1414,7 @@ hipError_t solve_box(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     X(256, 16, 8, 16, 16, 16, kZReg, 0, 0, 0)            \
     X(288, 12, 12, 24, 12, 16, kZSplit, 4, 16, 18)       \
     X(324, 18, 9, 18, 18, 9, kZGroups, 9, 0, 0)          \
-    X(384, 24, 8, 48, 8, 16, kZSplit, 8, 24, 16)         \
+    X(384, 24, 8, 48, 8, 16, kZSplit, 8, 16, 24)         \
     X(432, 36, 6, 36, 12, 12, kZGroups, 4, 0, 0)
 
 bool reg_size(int M) {
