@@ -860,8 +860,10 @@ struct XGeom {
     static constexpr int H = N1 * N2, M = 2 * H, T = N2;
     static constexpr int KS = N2 + 1;               // exchange: k1 stride (complex)
     static constexpr int LS = (N1 * KS + 31) / 32 * 32 + 8;   // exchange: line stride
-    // lines per block: a multiple of 4, at most 32, exchange buffer within 56 KiB
-    static constexpr int lpb(int l) { return (l > 4 && l * LS * 8 > 57344) ? lpb(l - 4) : l; }
+    // lines per block: a multiple of 4, at most 32, exchange buffer within
+    // 68 KiB (two blocks a CU; 32 lines of 432 points: 192 threads, three
+    // full wavefronts)
+    static constexpr int lpb(int l) { return (l > 4 && l * LS * 8 > 69632) ? lpb(l - 4) : l; }
     static constexpr int LPB = lpb((256 / T) / 4 * 4 > 32 ? 32 : (256 / T) / 4 * 4);
     static constexpr int NT = LPB * T;
     static constexpr bool SHFL = (T & (T - 1)) == 0 && 64 % T == 0;
@@ -1414,8 +1416,8 @@ hipError_t solve_box(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     X(256, 16, 8, 16, 16, 16, kZReg, 0, 0, 0)            \
     X(288, 12, 12, 24, 12, 16, kZSplit, 4, 16, 18)       \
     X(324, 18, 9, 18, 18, 9, kZGroups, 9, 0, 0)          \
-    X(384, 24, 8, 48, 8, 16, kZSplit, 8, 16, 24)         \
-    X(432, 36, 6, 36, 12, 12, kZGroups, 4, 0, 0)
+    X(384, 24, 8, 48, 8, 24, kZSplit, 8, 16, 24)         \
+    X(432, 36, 6, 36, 12, 18, kZGroups, 4, 0, 0)
 
 bool reg_size(int M) {
 #define FCM_REG_CASE(m, a, b, c, d, e, f, g, h, i) \
