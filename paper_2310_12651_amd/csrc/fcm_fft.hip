@@ -1404,19 +1404,19 @@ hipError_t solve_box(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
 // the y factorisation; kZSplit: one component a thread, M = ZN1 ZN2 split as
 // in four_step_split; kZLds: the LDS Stockham pass).
 #define FCM_REG_SIZES(X)                                 \
-    X(64, 8, 4, 8, 8, 32, kZReg, 0, 0, 0)                \
-    X(72, 18, 2, 12, 6, 36, kZReg, 0, 0, 0)              \
-    X(96, 12, 4, 24, 4, 48, kZReg, 0, 0, 0)              \
-    X(108, 18, 3, 18, 6, 27, kZReg, 0, 0, 0)             \
-    X(128, 8, 8, 16, 8, 32, kZReg, 0, 0, 0)              \
-    X(144, 12, 6, 12, 12, 18, kZReg, 0, 0, 0)            \
-    X(162, 9, 9, 18, 9, 27, kZReg, 0, 0, 0)              \
-    X(192, 24, 4, 24, 8, 32, kZReg, 0, 0, 0)             \
-    X(216, 18, 6, 36, 6, 18, kZSplit, 4, 18, 12)         \
-    X(256, 16, 8, 16, 16, 16, kZReg, 0, 0, 0)            \
-    X(288, 12, 12, 24, 12, 16, kZSplit, 4, 16, 18)       \
-    X(324, 18, 9, 18, 18, 9, kZGroups, 9, 0, 0)          \
-    X(384, 24, 8, 48, 8, 24, kZSplit, 8, 16, 24)         \
+    X(64, 8, 4, 8, 8, 32, kZReg, 0, 0, 0)            \
+    X(72, 18, 2, 12, 6, 36, kZReg, 0, 0, 0)          \
+    X(96, 12, 4, 24, 4, 48, kZSplit, 16, 12, 8)      \
+    X(108, 18, 3, 18, 6, 27, kZSplit, 6, 12, 9)      \
+    X(128, 8, 8, 16, 8, 32, kZGroups, 8, 0, 0)       \
+    X(144, 12, 6, 12, 12, 18, kZSplit, 4, 16, 9)     \
+    X(162, 9, 9, 18, 9, 27, kZGroups, 9, 0, 0)       \
+    X(192, 24, 4, 24, 8, 32, kZSplit, 4, 16, 12)     \
+    X(216, 18, 6, 36, 6, 18, kZSplit, 4, 18, 12)     \
+    X(256, 16, 8, 16, 16, 16, kZReg, 0, 0, 0)        \
+    X(288, 12, 12, 24, 12, 16, kZSplit, 4, 16, 18)   \
+    X(324, 18, 9, 18, 18, 9, kZGroups, 9, 0, 0)      \
+    X(384, 24, 8, 48, 8, 24, kZSplit, 8, 16, 24)     \
     X(432, 36, 6, 36, 12, 18, kZGroups, 4, 0, 0)
 
 bool reg_size(int M) {
