@@ -1416,7 +1416,7 @@ hipError_t solve_box(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
     X(256, 16, 8, 16, 16, 16, kZReg, 0, 0, 0)        \
     X(288, 12, 12, 24, 12, 16, kZSplit, 4, 16, 18)   \
     X(324, 18, 9, 18, 18, 9, kZGroups, 9, 0, 0)      \
-    X(384, 24, 8, 48, 8, 24, kZSplit, 8, 16, 24)     \
+    X(384, 24, 8, 48, 8, 24, kZGroups, 16, 0, 0)   \
     X(432, 36, 6, 36, 12, 18, kZGroups, 4, 0, 0)
 
 bool reg_size(int M) {
