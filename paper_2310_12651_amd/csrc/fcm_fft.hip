@@ -1308,8 +1308,10 @@ hipError_t solve_reg(const fcm_plan_impl* P, float* grid, hipStream_t st, hipEve
         using Z = ZGeomSplit<ZN1, ZN2, ZW>;
         hipLaunchKernelGGL((k_fft_z_solve_split<ZN1, ZN2, ZW>), dim3(Z::NG * M), dim3(Z::NT), 0, st,
                            spec, tw, proj_args(P, root));
-    } else
+    } else {
+        static_assert(ZMODE == kZLds, "z-pass mode");
         z_lds<float, 8>(P, spec, tw, st, proj_args(P, root));
+    }
     mark(3);
     if constexpr (fused) {
         mark(4);
