@@ -70,13 +70,15 @@ def test_brownian_in_a_rectangular_box():
     assert normwise(host(V), br.brownian(p, Y, xg, xp, 2.0)) < 1e-9
 
 
-@pytest.mark.parametrize("M", [(216,) * 3, (288,) * 3, (324,) * 3, (64, 64, 16), (32, 32, 8)],
+@pytest.mark.parametrize("M", [(96,) * 3, (108,) * 3, (128,) * 3, (144,) * 3, (162,) * 3, (192,) * 3,
+                               (216,) * 3, (288,) * 3, (324,) * 3, (384,) * 3, (64, 64, 16), (32, 32, 8)],
                          ids=lambda M: "x".join(map(str, M)))
 def test_brownian_grid_part_fp32_register_z_passes(M):
     """The grid part in FP32 on grids whose z pass takes one component per
-    thread group (216^3 and 288^3 with the split line, 324^3 with the four-step
-    of the y pass) or one column per thread (square boxes with 16 and 8 z
-    points), where the projection takes the square root of the Stokes
+    thread group (96^3, 108^3, 144^3, 192^3, 216^3 and 288^3 with the split
+    line; 128^3, 162^3, 324^3 and 384^3 with the four-step of the y pass) or one
+    column per thread (square boxes with 16 and 8 z points), where the
+    projection takes the square root of the Stokes
     multiplier: standard FCM (no pair part) against the oracle on the same
     noise.  The oracle's FFT runs on scipy threads at these sizes."""
     import os
