@@ -7,7 +7,8 @@ equals the support (48 x 12 x 24, M_G = 12: every support covers all of y and th
 spreading tiles are one row wide); the paper's rod grid 512 x 512 x 8 with
 M_G = 10 and two more boxes whose support is longer than the z axis (M_G = 12
 on 8 points, M_G = 16 on 12: the support wraps onto itself), and the paper's
-filament grid 256 x 256 x 16; every operator and the whole mobility, FP64 (1e-10 normwise) and FP32 bulk (1e-5).  Also the copy
+filament grid 256 x 256 x 16, and a 288 x 288 x 16 box (register passes of 288
+with a partial last block of x lines); every operator and the whole mobility, FP64 (1e-10 normwise) and FP32 bulk (1e-5).  Also the copy
 identity of the oracle's box pins, on the GPU: copies of a cube along one axis
 keep the cube's velocities.
 """
@@ -39,6 +40,9 @@ BOXES = {
     "fold48x48x12": dict(L=(24.0, 24.0, 6.0), M=(48, 48, 12), Sigma=0.75, M_G=16, R_c=2.9, N=40),
     # the paper's filament grid (Sec. 6.3, 256 x 256 x 16)
     "fil256x256x16": dict(L=(204.8, 204.8, 12.8), M=(256, 256, 16), Sigma=0.8, M_G=10, R_c=4.4, N=1500),
+    # register x and y passes of 288 (x lines staged through LDS, the last block
+    # of 20 lines partly past the 3 x 288 x 16 lines) around the column z pass
+    "sq288x288x16": dict(L=(144.0, 144.0, 8.0), M=(288, 288, 16), Sigma=0.6, M_G=10, R_c=3.0, N=60),
 }
 
 
