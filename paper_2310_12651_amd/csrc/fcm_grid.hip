@@ -570,7 +570,11 @@ __device__ inline float4 plane_load4(const float* plane, int n, unsigned col) {
 // with P_c = sum_z g_z sum_x g_xy u_c, R_c = sum_z g_z sum_x g_xy dx^2 u_c,
 // PD2_c = sum_z g_z dz^2 sum_x g_xy u_c, PD_c = sum_z g_z dz sum_x g_xy u_c,
 // Q_c = sum_z g_z sum_x g_xy dx u_c.
-template <bool OMEGA>
+// WIDE (row-major layout, M_G <= 16): the chunks start at the support's first
+// point x0 instead of x0 & ~3, so 16 rows x 4 chunks cover an M_G = 16 support
+// exactly; the 16-byte loads are then only 4-byte aligned, and a chunk that
+// crosses the end of a row is read as four single values.
+template <bool OMEGA, bool WIDE = false>
 __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restrict__ rec,
                                                  const float* __restrict__ grid, double* __restrict__ V,
                                                  double* __restrict__ W, GridArgs<float> a,
@@ -604,9 +608,11 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
     }
     // lane -> support row j, chunk c of four x points starting at the aligned x0 & ~3
     const int j = lane >> 2, c = lane & 3;
-    const int x0 = r.s[0], off0 = x0 & 3;
+    const int x0 = r.s[0], off0 = WIDE ? 0 : x0 & 3;
     int xs = (x0 - off0) + 4 * c;
     if (xs >= Mx) xs -= Mx;
+    // WIDE: a chunk running past the end of the row wraps to its start
+    const bool split = WIDE && xs > Mx - 4;
     const bool rowok = j < MG;
     int yy = r.s[1] + (rowok ? j : 0);
     if (yy >= My) yy -= My;
@@ -637,10 +643,22 @@ __global__ __launch_bounds__(256) void k_interp4(const GridRec<float>* __restric
         const ZTab<float> e = zt[wave][k];
         const float* pz = grid + (size_t)z * nplane;
         float4 u[3] = {make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0)};
-        if (need) {
+        if (need && !split) {
             u[0] = plane_load4(pz, nplane, col);
             u[1] = plane_load4(pz + M3, nplane, col);
             u[2] = plane_load4(pz + 2 * M3, nplane, col);
+        } else if (need) {
+            // xs + e past the row end wraps back by Mx points (4 Mx bytes)
+            const unsigned cw = col - 4u * (unsigned)Mx;
+            const unsigned c1 = xs + 1 < Mx ? col + 4u : cw + 4u;
+            const unsigned c2 = xs + 2 < Mx ? col + 8u : cw + 8u;
+            const unsigned c3 = xs + 3 < Mx ? col + 12u : cw + 12u;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                const float* pc = pz + cc * M3;
+                u[cc] = make_float4(plane_load(pc, nplane, col), plane_load(pc, nplane, c1),
+                                    plane_load(pc, nplane, c2), plane_load(pc, nplane, c3));
+            }
         }
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
@@ -946,12 +964,12 @@ hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W,
     dim3 g((unsigned)((P->N + 3) / 4)), b(256);
     const GridRec<R>* rec = (const GridRec<R>*)P->grec;
     if constexpr (sizeof(R) == sizeof(float)) {
-        // Packed kernels need quads of four x points (M divisible by 4) and one
-        // width.  In the tiled layout the two lanes of a support row read one
-        // 8 x 4 tile's halves per load, so several particles per wavefront pay
-        // (M_G <= 16); in the row-major layout rows are a plane row apart and
-        // only the four-lane form (M_G <= 13) reads few enough cache lines per
-        // byte to beat the one-column-per-lane kernel.
+        // Packed kernels need one width.  In the tiled layout the two lanes of
+        // a support row read one 8 x 4 tile's halves per load, so several
+        // particles per wavefront pay (M_G <= 16); in the row-major layout rows
+        // are a plane row apart and the four-lane form reads fewest cache lines
+        // per byte: aligned quads for M divisible by 4 and M_G <= 13, quads from
+        // the support's first point otherwise (M_G <= 16).
         if (P->M % 4 == 0 && a.same_width && tiled && P->MG <= 16 &&
             (size_t)P->M * P->My * P->Mz <= (size_t)512 * 512 * 512) {
             const int ppw = std::min(4, 32 / P->MG);
@@ -974,6 +992,13 @@ hipError_t interp_r(const fcm_plan_impl* P, const R* grid, double* V, double* W,
                 hipLaunchKernelGGL(k_interp4<false>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
             else
                 hipLaunchKernelGGL(k_interp4<true>, g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
+            return hipGetLastError();
+        }
+        if (!tiled && a.same_width && P->MG <= 16 && P->M >= 4) {
+            if (W == nullptr)
+                hipLaunchKernelGGL((k_interp4<false, true>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
+            else
+                hipLaunchKernelGGL((k_interp4<true, true>), g, b, 0, st, rec, grid, V, W, a, scaleV, scaleW, corr);
             return hipGetLastError();
         }
     }
