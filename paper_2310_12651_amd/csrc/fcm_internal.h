@@ -119,7 +119,7 @@ struct PairArgs {
     int store;                     // 1 = write the corrections, 0 = add them
     // the six Gaussian widths of the corrections: squared width s, erfc
     // argument scale 1/sqrt(2 s), exponent scale -1/(2 s), norm (2 pi s)^(-3/2)
-    double wsq[6], escale[6], gexp[6], gnorm[6];
+    double wsq[6], escale[6], gnorm[6];
     // constants of the correction blocks (d = sigma^2 - Sigma^2, s2 = 2 Sigma^2,
     // sb = Sigma^2 + Sigma_D^2): 1/(8 pi eta), 1/(2 eta), d/eta, d^2/(4 eta s2),
     // d/(4 eta sb), 1/s2
