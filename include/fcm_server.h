@@ -3,8 +3,8 @@
  * mobility evaluations on one GPU).
  *
  * Each request is one application of the fast-FCM mobility (Sec. 4 of Su &
- * Keaveny, arXiv 2310.12651) with its own particle count, box, kernel width,
- * grid and cut-off.  A worker thread inside the library admits pending requests
+ * Keaveny, arXiv 2310.12651) with its own particle count, box (cubic, or
+ * rectangular through fcm_server_submit_box), kernel width, grid and cut-off.  A worker thread inside the library admits pending requests
  * whenever a slot is free and the device bytes of the plan the request needs fit
  * the server's budget, runs up to `slots` requests at once on separate
  * (non-blocking, default-priority) HIP streams so their kernels overlap on the
@@ -87,6 +87,16 @@ int fcm_server_create(fcm_server_t* out, const fcm_server_options* opt);
 /* Queue a request; *ticket identifies it.  The parameters are validated here
  * (FCM_EINVAL / FCM_ERANGE as for fcm_plan); FCM_EBUSY if the queue is full. */
 int fcm_server_submit(fcm_server_t s, const fcm_request* req, int64_t* ticket);
+/* Queue a request on a rectangular periodic box, as fcm_plan_box: L (host, 3
+ * sides along x, y, z) and grid (host, 3 point counts, one grid spacing on all
+ * axes) replace the request's own L and grid fields, which are ignored; the
+ * library copies both arrays.  The rod and filament runs of Sec. 6.3 use such
+ * grids (512 x 512 x 8, 256 x 256 x 16).  A cached plan is re-bound only to a
+ * request with the same three grid sizes.  Errors: as fcm_server_submit, and as
+ * fcm_plan_box for the box (unequal spacings, a support longer than an axis it
+ * may not wrap on); FCM_EINVAL if L or grid is NULL. */
+int fcm_server_submit_box(fcm_server_t s, const fcm_request* req, const double L[3], const int grid[3],
+                          int64_t* ticket);
 /* *state = 0 queued, 1 running, 2 done; returns the request's status once done. */
 int fcm_server_poll(fcm_server_t s, int64_t ticket, int* state);
 /* Block until the request is done; queue_ms = submit -> launch, run_ms =

@@ -8,8 +8,9 @@
 // are taken in arrival order, but one that has to wait for memory held by
 // running requests is passed by later ones that fit (at most kMaxBypass times;
 // then admission holds for it, so large requests are not starved).
-// Plans are cached and re-bound to later requests with the same grid, support
-// and precision, so grids, twiddles and sort/cell buffers stay resident;
+// Plans are cached and re-bound to later requests with the same grid (all three
+// axes: a request may name a rectangular box), support and precision, so grids,
+// twiddles and sort/cell buffers stay resident;
 // idle plans are freed least-recently-used first when room is needed.
 #include <algorithm>
 #include <chrono>
@@ -42,6 +43,8 @@ constexpr int kMaxBypass = 32;
 
 struct Req {
     fcm_request r;
+    double L3[3] = {0.0, 0.0, 0.0};   // box sides (all r.L for a cubic request)
+    int g3[3] = {0, 0, 0};            // grid points per axis
     int64_t ticket = 0;
     int state = 0;   // 0 queued, 1 running, 2 done
     int status = FCM_OK;
@@ -102,8 +105,10 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
-// derive the plan scalars of a request (validation included)
-int derive_request(const fcm_server_options& o, const fcm_request& r, fcm_plan_impl* d) {
+// derive the plan scalars of a request on the box L3 with grid g3 (validation
+// included, as fcm_plan_box)
+int derive_request(const fcm_server_options& o, const fcm_request& r, const double L3[3], const int g3[3],
+                   fcm_plan_impl* d) {
     fcm_options opt;
     fcm_options_default(&opt);
     opt.eta = r.eta > 0.0 ? r.eta : 1.0;
@@ -111,8 +116,6 @@ int derive_request(const fcm_server_options& o, const fcm_request& r, fcm_plan_i
     opt.precision = o.precision;
     opt.kahan = o.kahan;
     memset(d, 0, sizeof(*d));
-    const double L3[3] = {r.L, r.L, r.L};
-    const int g3[3] = {r.grid, r.grid, r.grid};
     return fcm::plan_derive(d, r.N, L3, r.a, r.sigma_delta, g3, r.r_cut, &opt);
 }
 
@@ -141,7 +144,8 @@ CachedPlan* fcm_server_impl::plan_for_locked(const fcm_plan_impl& d, int* status
     CachedPlan* best = nullptr;
     for (CachedPlan* c : cache) {
         const fcm_plan_impl* P = c->P;
-        if (c->busy || P->M != d.M || P->MG != d.MG || P->precision != d.precision ||
+        if (c->busy || P->M != d.M || P->My != d.My || P->Mz != d.Mz || P->MG != d.MG ||
+            P->precision != d.precision ||
             P->kahan != d.kahan || P->Ncap < d.N || P->cells_cap < d.ncells)
             continue;
         if (!best || P->Ncap < best->P->Ncap) best = c;
@@ -247,7 +251,7 @@ bool fcm_server_impl::admit_locked() {
         if (!free_slot) break;
         Req* r = queue[i];
         fcm_plan_impl d;
-        int st = derive_request(opt, r->r, &d);
+        int st = derive_request(opt, r->r, r->L3, r->g3, &d);
         CachedPlan* c = nullptr;
         const int64_t pts = st == FCM_OK ? (int64_t)d.M * d.My * d.Mz : 0;
         // the grid points in flight stay within max_points (one request always runs)
@@ -323,6 +327,62 @@ void fcm_server_impl::run() {
     }
 }
 
+namespace {
+
+// validate a request on the box L3 with grid g3 and queue it
+int submit_request(fcm_server_t s, const fcm_request* req, const double L3[3], const int g3[3],
+                   int64_t* ticket) {
+    if (!s || !req || !ticket || !req->pos || !req->F || !req->V) return FCM_EINVAL;
+    fcm_plan_impl d;
+    const int st = derive_request(s->opt, *req, L3, g3, &d);
+    if (st != FCM_OK) return st;
+    Req* r = new (std::nothrow) Req;
+    if (!r) return FCM_ENOMEM;
+    r->r = *req;
+    for (int k = 0; k < 3; ++k) {
+        r->L3[k] = L3[k];
+        r->g3[k] = g3[k];
+    }
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stopping) {
+            delete r;
+            return FCM_EINVAL;
+        }
+        if ((int)s->queue.size() >= s->opt.max_queue) {
+            delete r;
+            return FCM_EBUSY;
+        }
+        if (req->after_stream) {
+            // the request runs after the work the caller's stream holds now
+            hipEvent_t ev = nullptr;
+            if (!s->free_events.empty()) {
+                ev = s->free_events.back();
+                s->free_events.pop_back();
+            } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                delete r;
+                return FCM_EDEVICE;
+            }
+            if (hipEventRecord(ev, (hipStream_t)req->after_stream) != hipSuccess) {
+                s->free_events.push_back(ev);
+                delete r;
+                return FCM_EDEVICE;
+            }
+            r->after = ev;
+        }
+        r->ticket = s->next_ticket++;
+        s->reqs[r->ticket] = r;
+        s->queue.push_back(r);
+        s->stats.submitted++;
+        *ticket = r->ticket;
+    }
+    s->work_cv.notify_one();
+    return FCM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int fcm_server_options_default(fcm_server_options* o) {
@@ -384,49 +444,16 @@ int fcm_server_create(fcm_server_t* out, const fcm_server_options* opt_in) {
 }
 
 int fcm_server_submit(fcm_server_t s, const fcm_request* req, int64_t* ticket) {
-    if (!s || !req || !ticket || !req->pos || !req->F || !req->V) return FCM_EINVAL;
-    fcm_plan_impl d;
-    const int st = derive_request(s->opt, *req, &d);
-    if (st != FCM_OK) return st;
-    Req* r = new (std::nothrow) Req;
-    if (!r) return FCM_ENOMEM;
-    r->r = *req;
-    r->t_submit = Clock::now();
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->stopping) {
-            delete r;
-            return FCM_EINVAL;
-        }
-        if ((int)s->queue.size() >= s->opt.max_queue) {
-            delete r;
-            return FCM_EBUSY;
-        }
-        if (req->after_stream) {
-            // the request runs after the work the caller's stream holds now
-            hipEvent_t ev = nullptr;
-            if (!s->free_events.empty()) {
-                ev = s->free_events.back();
-                s->free_events.pop_back();
-            } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-                delete r;
-                return FCM_EDEVICE;
-            }
-            if (hipEventRecord(ev, (hipStream_t)req->after_stream) != hipSuccess) {
-                s->free_events.push_back(ev);
-                delete r;
-                return FCM_EDEVICE;
-            }
-            r->after = ev;
-        }
-        r->ticket = s->next_ticket++;
-        s->reqs[r->ticket] = r;
-        s->queue.push_back(r);
-        s->stats.submitted++;
-        *ticket = r->ticket;
-    }
-    s->work_cv.notify_one();
-    return FCM_OK;
+    if (!req) return FCM_EINVAL;
+    const double L3[3] = {req->L, req->L, req->L};
+    const int g3[3] = {req->grid, req->grid, req->grid};
+    return submit_request(s, req, L3, g3, ticket);
+}
+
+int fcm_server_submit_box(fcm_server_t s, const fcm_request* req, const double L[3], const int grid[3],
+                          int64_t* ticket) {
+    if (!L || !grid) return FCM_EINVAL;
+    return submit_request(s, req, L, grid, ticket);
 }
 
 int fcm_server_poll(fcm_server_t s, int64_t ticket, int* state) {

@@ -34,7 +34,8 @@ class ServerStats(ctypes.Structure):
 
 
 SERVER_EXPORTS = ["fcm_server_options_default", "fcm_server_create", "fcm_server_submit",
-                  "fcm_server_poll", "fcm_server_wait", "fcm_server_get_stats", "fcm_server_destroy"]
+                  "fcm_server_submit_box", "fcm_server_poll", "fcm_server_wait", "fcm_server_get_stats",
+                  "fcm_server_destroy"]
 
 _bound = False
 
@@ -48,6 +49,8 @@ def _lib():
             "fcm_server_options_default": ([ctypes.POINTER(ServerOptions)], ci),
             "fcm_server_create": ([ctypes.POINTER(vp), ctypes.POINTER(ServerOptions)], ci),
             "fcm_server_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(i64)], ci),
+            "fcm_server_submit_box": ([vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ci), ctypes.POINTER(i64)], ci),
             "fcm_server_poll": ([vp, i64, ctypes.POINTER(ci)], ci),
             "fcm_server_wait": ([vp, i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ci),
             "fcm_server_get_stats": ([vp, ctypes.POINTER(ServerStats)], ci),
@@ -84,18 +87,28 @@ class Server:
     def submit(self, N, L, a, Sigma, grid, r_cut, pos, F, T=None, V=None, Omega=None, support=0, eta=1.0,
                stream=None):
         """Queue one evaluation; it runs after the work queued so far on
-        ``stream`` (default: the current stream, where torch wrote the inputs)."""
+        ``stream`` (default: the current stream, where torch wrote the inputs).
+        ``L`` and ``grid`` may be three values (x, y, z) for a rectangular box
+        (fcm_server_submit_box)."""
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
-        r = Request(N=int(N), L=float(L), a=float(a), sigma_delta=float(Sigma), grid=int(grid),
+        box = hasattr(L, "__len__") or hasattr(grid, "__len__")
+        L3 = tuple(float(v) for v in L) if hasattr(L, "__len__") else (float(L),) * 3
+        g3 = tuple(int(v) for v in grid) if hasattr(grid, "__len__") else (int(grid),) * 3
+        r = Request(N=int(N), L=L3[0], a=float(a), sigma_delta=float(Sigma), grid=g3[0],
                     r_cut=float(r_cut), support=int(support), eta=float(eta),
                     pos=pos.data_ptr(), F=F.data_ptr(), T=None if T is None else T.data_ptr(),
                     V=V.data_ptr(), Omega=None if Omega is None else Omega.data_ptr(),
                     after_stream=stream.cuda_stream)
         t = ctypes.c_int64()
-        st = _lib().fcm_server_submit(self._h, ctypes.byref(r), ctypes.byref(t))
-        _check(st, "fcm_server_submit")
+        if box:
+            st = _lib().fcm_server_submit_box(self._h, ctypes.byref(r), (ctypes.c_double * 3)(*L3),
+                                              (ctypes.c_int * 3)(*g3), ctypes.byref(t))
+            _check(st, "fcm_server_submit_box")
+        else:
+            st = _lib().fcm_server_submit(self._h, ctypes.byref(r), ctypes.byref(t))
+            _check(st, "fcm_server_submit")
         return t.value
 
     def poll(self, ticket):
