@@ -28,6 +28,13 @@
  *    and return without waiting; results are ready when the stream reaches
  *    them.  A plan owns scratch buffers, so concurrent calls on one plan race:
  *    use one plan per concurrently used stream.
+ *  - fcm_mobility and fcm_mobility_repeat allocate nothing and never wait on
+ *    the host, so they may be captured into a HIP graph (stream capture on a
+ *    non-null stream; the pair correction's side stream joins the capture
+ *    through the plan's own events).  A replay reads the particle arrays named
+ *    at capture, so new inputs are written into those arrays.  The graph refers
+ *    to the plan's buffers, side stream and events: destroy every such graph
+ *    before fcm_plan_destroy.
  *  - Grid fields exchanged by the stage calls are DEVICE buffers of
  *    3 * grid^3 values in the plan's grid precision (double for FCM_FP64,
  *    float for FCM_FP32_BULK), component-major, x fastest:
