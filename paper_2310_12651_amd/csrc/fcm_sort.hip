@@ -77,9 +77,13 @@ __global__ void k_hash(const double* __restrict__ pos, HashArgs h, int* __restri
     if (i >= h.N) return;
     int bad = 0;
     int s[3], c[3];
+    double y[3];
+    // the three coordinates are loaded before the wrap's branches
+#pragma unroll
+    for (int a = 0; a < 3; ++a) y[a] = pos[3 * (int64_t)i + a];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double w = wrap_coord(pos[3 * (int64_t)i + a], h.Lv[a], &bad);
+        double w = wrap_coord(y[a], h.Lv[a], &bad);
         s[a] = wrap_index(support_start(w, h.dx, h.MG), h.Mv[a]);
         int cc = (int)floor(w / h.cw[a]);
         c[a] = cc < 0 ? 0 : (cc >= h.mc[a] ? h.mc[a] - 1 : cc);
@@ -93,13 +97,13 @@ __global__ void k_hash(const double* __restrict__ pos, HashArgs h, int* __restri
     int cell = c[0] + h.mc[0] * (c[1] + h.mc[1] * c[2]);
     keys[i] = bin;
     keys[h.N + i] = cell;
-    ranks[i] = atomicAdd(&counts[bin], 1);
-    if (h.ident) {
-        ranks[h.N + i] = i;
-        if (i == 0) counts[h.nbins] = h.N;
-    } else {
-        ranks[h.N + i] = atomicAdd(&counts[h.nbins + cell], 1);
-    }
+    // both counter increments are issued before either rank is stored, so
+    // their round trips overlap
+    const int rb = atomicAdd(&counts[bin], 1);
+    const int rc = h.ident ? i : atomicAdd(&counts[h.nbins + cell], 1);
+    if (h.ident && i == 0) counts[h.nbins] = h.N;
+    ranks[i] = rb;
+    ranks[h.N + i] = rc;
 }
 
 // block-wide inclusive scan of one int per thread (blockDim = NT)
