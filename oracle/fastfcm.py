@@ -221,6 +221,30 @@ def stokes_solve(p, f, workers=None):
     return np.real(ifftn(uh, axes=(1, 2, 3)))
 
 
+def stokes_plane_wave(p, j, A, phi, idx):
+    """The inverse Stokes operator of Sec. 2.1 step 2 (App. A) applied to one
+    real Fourier mode, in closed form: f(x) = A cos(k.x + phi) with
+    k_d = 2 pi j_d / L_d gives u(x) = (I - k k^T / k^2) A cos(k.x + phi) /
+    (eta k^2), for an integer mode j != 0 with |j_d| < M_d / 2 on every axis
+    (neither the zero mode nor an index-M/2 mode is involved).
+
+    idx: integer grid indices, shape (n, 3) as (x, y, z), the points
+    idx * dx.  The phase is 2 pi sum_d ((j_d idx_d) mod M_d) / M_d + phi,
+    exact in its integer part at any grid size.  Returns u at the points,
+    shape (n, 3).
+    """
+    j = np.asarray(j, dtype=np.int64)
+    Mv = np.asarray(p.Mv, dtype=np.int64)
+    if not np.any(j != 0) or np.any(2 * np.abs(j) >= Mv):
+        raise ValueError("mode must be nonzero with |j_d| < M_d / 2")
+    k = 2.0 * np.pi * j / p.Lv
+    k2 = float(k @ k)
+    A = np.asarray(A, dtype=np.float64)
+    amp = (A - k * (k @ A) / k2) / (p.eta * k2)
+    frac = np.sum(np.mod(np.asarray(idx, dtype=np.int64) * j, Mv) / Mv, axis=1)
+    return np.cos(2.0 * np.pi * frac + phi)[:, None] * amp[None, :]
+
+
 def interp(p, Y, u, want_omega=True, chunk=2048):
     """J~[u] and N~[u] (Sec. 3.1 eq. avg_particle_vel_mod, Sec. 3.4
     eq. avg_particle_rot_mod) by the trapezoid rule on the M_G^3 support

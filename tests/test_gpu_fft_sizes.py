@@ -2,13 +2,18 @@
 FP32 and the FP64 path (whose passes use the LDS kernels) against the oracle's
 at every size, 64^3 to 432^3 (the request stream's largest grids), and the
 whole mobility, where the solve hands the interpolation a tiled field, against
-the FP64 path.
+the FP64 path.  Above 432^3, up to the largest cube a plan accepts (1024^3;
+LDS passes), the solve of single Fourier modes, one per solve, against their
+closed form (ff.stokes_plane_wave), at 4096 sampled grid points.
 
 Inputs: a white-noise field (seeded) for the solve; 400 random particles with
 N(0, 1) forces and torques in a box of side M (dx = 1, Sigma = 1, M_G = 10,
-R_c = 5.5) for the mobility.
+R_c = 5.5) for the mobility; seeded modes for the large grids, one at a time
+(FP64: along x, along y one below the Nyquist index, a mixed one with a z
+index one below Nyquist, a random one; FP32: along x and two mixed ones).
 """
 
+import math
 import os
 import zlib
 
@@ -70,3 +75,55 @@ def test_mobility_fp32_register_passes(M):
         plan.close()
     assert normwise(out[1][0], out[0][0]) < 1e-5, M
     assert normwise(out[1][1], out[0][1]) < 1e-5, M
+
+
+LARGE_SIZES = [486, 512, 576, 648, 768, 864, 972, 1024]
+
+
+def _large_modes(M, prec):
+    """Seeded modes: FP64 takes one along x, one along y one below the Nyquist
+    index, a mixed one with a z index one below Nyquist and a random one; FP32
+    takes the mode along x and two mixed ones (|j_d| <= M/6): a mode along one
+    axis with a large index rounds to FP32 in a one-dimensional pattern whose
+    low-k content the solve amplifies by |j|^2 (1e-4 at 768^3 with an
+    independent single-precision FFT too), which fields spread from Gaussians
+    do not have."""
+    rng = np.random.default_rng(zlib.crc32(f"large{M}-{prec}".encode()))
+    h = M // 2 - 1
+    if prec == 0:
+        js = [(1, 0, 0), (0, h, 0), (-(M // 3), 7, h - 2), tuple(int(v) for v in rng.integers(-h, h + 1, size=3))]
+    else:
+        q = M // 8
+        js = [(1, 0, 0), (-(M // 6), 7, q), tuple(int(v) for v in rng.integers(-q, q + 1, size=3))]
+    return [(j, rng.normal(size=3), float(rng.uniform(0.0, 2.0 * np.pi))) for j in js]
+
+
+@pytest.mark.parametrize("M", LARGE_SIZES)
+def test_solve_large_grids_against_plane_waves(M):
+    """One solve per mode, each against its own closed form (in a sum of modes
+    the solve divides by k^2, so rounding of the larger modes' forcing lands
+    on the smallest k amplified by up to (M / 2)^2)."""
+    import torch
+    p = ff.Params(L=float(M), M=M, a=1.0, Sigma=1.0, M_G=10, R_c=0.0)
+    idx = np.random.default_rng(zlib.crc32(f"pts{M}".encode())).integers(0, M, size=(4096, 3))
+    n = torch.arange(M, device="cuda")
+    it = torch.as_tensor(idx, device="cuda")
+    for prec, tol in [(1, 1e-5), (0, 1e-10)]:
+        plan = _plan(M, 1, prec)
+        try:
+            for j, A, phi in _large_modes(M, prec):
+                # the field (3, z, y, x): A_c cos(2 pi ((j . n) mod M) / M + phi)
+                ph = (j[0] * n[None, None, :] + j[1] * n[None, :, None] + j[2] * n[:, None, None]) % M
+                wave = torch.cos(ph.to(torch.float64) * (2.0 * math.pi / M) + phi)
+                del ph
+                g = torch.stack([(float(A[c]) * wave).to(plan.grid_dtype) for c in range(3)])
+                del wave
+                plan.solve(g)
+                uh = host(g[:, it[:, 2], it[:, 1], it[:, 0]].T).astype(np.float64)
+                del g
+                e = normwise(uh, ff.stokes_plane_wave(p, j, A, phi, idx))
+                print(f"large solve M={M} prec={prec} j={j} err={e:.2e}", flush=True)
+                assert e < tol, (M, prec, j, e)
+        finally:
+            plan.close()
+            torch.cuda.empty_cache()

@@ -2,7 +2,9 @@
 
 Each test checks the oracle against something other than itself:
 
-* the Fourier Stokes solve against a brute-force discrete Fourier sum;
+* the Fourier Stokes solve against a brute-force discrete Fourier sum, and its
+  closed form for single Fourier modes (which the GPU tests use on grids too
+  large for the oracle's full solve) against the solve itself;
 * spreading against the moment identities of the kernels (total force, and
   first moment x cross f = T, which fixes the sign of the torque spreading,
   Sec. 3.4);
@@ -19,6 +21,7 @@ Each test checks the oracle against something other than itself:
 """
 
 import math
+import zlib
 
 import numpy as np
 import pytest
@@ -92,6 +95,37 @@ def test_stokes_solve_equals_direct_fourier_sum(M):
     f = np.random.default_rng(1).normal(size=(3, M, M, M))
     u = ff.stokes_solve(p, f)
     assert np.allclose(u, _dft_stokes(p, f), rtol=0, atol=1e-13 * np.abs(u).max())
+
+
+@pytest.mark.parametrize("L,M,j", [
+    (5.0, 12, (1, 0, 0)), (5.0, 12, (5, -3, 2)), (5.0, 18, (0, 0, -8)),
+    ((6.0, 4.0, 3.0), (24, 16, 12), (11, -7, 5)), ((6.0, 4.0, 3.0), (24, 16, 12), (-2, 0, 1)),
+])
+def test_plane_wave_closed_form_equals_solve(L, M, j):
+    """A sum of one mode's closed-form solution over every grid point equals
+    the Fourier solve of the sampled mode (cube and box, eta != 1, modes up to
+    one below the Nyquist index)."""
+    p = ff.Params(L=L, M=M, a=A, Sigma=0.8, M_G=4, R_c=0.0, eta=1.7)
+    rng = np.random.default_rng(zlib.crc32(repr((L, M, j)).encode()))
+    Av, phi = rng.normal(size=3), rng.uniform(0.0, 2.0 * np.pi)
+    Mx, My, Mz = p.Mv
+    idx = np.stack(np.meshgrid(np.arange(Mx), np.arange(My), np.arange(Mz), indexing="ij"), -1).reshape(-1, 3)
+    # the forcing sampled on the grid: A cos(k.x + phi) at x = idx * dx
+    k = 2.0 * np.pi * np.asarray(j) / p.Lv
+    wave = np.cos((idx * p.dx) @ k + phi)
+    f = (Av[:, None] * wave[None, :]).reshape(3, Mx, My, Mz)
+    u = ff.stokes_solve(p, f).reshape(3, -1).T
+    uc = ff.stokes_plane_wave(p, j, Av, phi, idx)
+    assert np.allclose(u, uc, rtol=0, atol=1e-12 * np.abs(uc).max())
+    # divergence-free amplitude and the 1/k^2 decay
+    assert abs(np.sum(k * uc[0])) < 1e-12 * np.abs(uc).max() * np.sqrt(k @ k)
+
+
+def test_plane_wave_rejects_zero_and_nyquist_modes():
+    p = ff.Params(L=5.0, M=12, a=A, Sigma=0.8, M_G=4, R_c=0.0)
+    for j in [(0, 0, 0), (6, 0, 0), (0, -6, 1)]:
+        with pytest.raises(ValueError):
+            ff.stokes_plane_wave(p, j, (1.0, 0.0, 0.0), 0.0, np.zeros((1, 3), dtype=np.int64))
 
 
 def _spread_fns():
