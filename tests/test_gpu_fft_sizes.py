@@ -127,3 +127,35 @@ def test_solve_large_grids_against_plane_waves(M):
         finally:
             plan.close()
             torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("M,Mb", [(1024, 128), (972, 162), (864, 108)])
+def test_mobility_largest_grids_by_periodic_copies(M, Mb):
+    """The whole mobility on the largest cubes (every stage at these sizes:
+    sort, spread and interpolation on the row-major field, LDS passes, pair
+    correction with 128 cells an axis) against the oracle: (M/Mb)^3 copies of
+    an Mb^3 cube fill the M^3 box, and by periodicity every copy's particles
+    move as the cube's, which the oracle computes (FP64 1e-10, FP32 1e-5)."""
+    k = M // Mb
+    rng = np.random.default_rng(zlib.crc32(f"copies{M}".encode()))
+    N = 6
+    Y = rng.uniform(0.0, float(Mb), size=(N, 3))
+    F, T = rng.normal(size=(N, 3)), rng.normal(size=(N, 3))
+    p = ff.Params(L=float(Mb), M=Mb, a=1.0, Sigma=1.0, M_G=10, R_c=5.5)
+    Vr, Wr = ff.mobility(p, Y, F, T)
+    shifts = np.stack(np.meshgrid(*[np.arange(k)] * 3, indexing="ij"), -1).reshape(-1, 1, 3) * float(Mb)
+    Yb = (Y[None] + shifts).reshape(-1, 3)
+    Fb, Tb = np.tile(F, (k ** 3, 1)), np.tile(T, (k ** 3, 1))
+    for prec, tol in [(1, 1e-5), (0, 1e-10)]:
+        from paper_2310_12651_amd import Plan
+        plan = Plan(len(Yb), float(M), 1.0, 1.0, M, 5.5, support=10, precision=prec)
+        try:
+            V, W = plan.mobility(dev(Yb), dev(Fb), dev(Tb))
+            Vb, Wb = host(V).reshape(k ** 3, N, 3), host(W).reshape(k ** 3, N, 3)
+            assert plan.last_error() == 0
+        finally:
+            plan.close()
+        ev = max(normwise(Vb[c], Vr) for c in range(k ** 3))
+        ew = max(normwise(Wb[c], Wr) for c in range(k ** 3))
+        print(f"copies M={M} prec={prec} V={ev:.2e} W={ew:.2e}", flush=True)
+        assert ev < tol and ew < tol, (M, prec, ev, ew)
