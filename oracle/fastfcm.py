@@ -320,15 +320,21 @@ def pair_correction(p, Y, F, T=None, targets=None):
         cand = cand[cand != n]
         x = min_image(Yw[n][None, :] - Yw[cand], p.Lv)
         r = np.sqrt(np.sum(x * x, axis=1))
-        sel = r < p.R_c
+        # a neighbour at the same point (r = 0 exactly): the corrections take
+        # their r -> 0 limits of App. B, the self-correction values (the
+        # force-torque blocks are odd in x and vanish there)
+        same = cand[r == 0.0]
+        dV[t] += cf.self_correction_VF(p.a, sg, Sg, eta) * F[same].sum(axis=0)
+        dW[t] += cf.self_correction_OT(p.a, SD, eta) * Tq[same].sum(axis=0)
+        sel = (r < p.R_c) & (r > 0.0)
         cand, x = cand[sel], x[sel]
         if len(cand):
             CVF = cf.correction_VF(x, sg, Sg, eta)
             CVT = cf.correction_VT(x, sg, sD, Sg, SD, eta)
             COF = cf.correction_OF(x, sg, sD, Sg, SD, eta)
             COT = cf.correction_OT(x, sD, SD, eta)
-            dV[t] = np.einsum("pij,pj->i", CVF, F[cand]) + np.einsum("pij,pj->i", CVT, Tq[cand])
-            dW[t] = np.einsum("pij,pj->i", COF, F[cand]) + np.einsum("pij,pj->i", COT, Tq[cand])
+            dV[t] += np.einsum("pij,pj->i", CVF, F[cand]) + np.einsum("pij,pj->i", CVT, Tq[cand])
+            dW[t] += np.einsum("pij,pj->i", COF, F[cand]) + np.einsum("pij,pj->i", COT, Tq[cand])
         dV[t] += cf.self_correction_VF(p.a, sg, Sg, eta) * F[n]
         dW[t] += cf.self_correction_OT(p.a, SD, eta) * Tq[n]
     return dV, dW

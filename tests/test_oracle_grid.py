@@ -336,3 +336,30 @@ def test_targets_subset_matches_full_evaluation():
     tg = np.array([7, 2, 19])
     Vs, Ws = ff.mobility(p, Y, F, T, targets=tg)
     assert np.allclose(Vs, V[tg], rtol=0, atol=1e-15) and np.allclose(Ws, W[tg], rtol=0, atol=1e-15)
+
+
+def test_pair_correction_at_coincident_centres_is_the_limit():
+    """Two particles at the same point: the pair correction takes the r -> 0
+    limits of App. B, so it is finite (the closed forms divide by r) and equals
+    the mean of the corrections with the second particle moved 1e-3 sigma
+    either way (the odd force-torque blocks cancel; the rest approaches its
+    limit as r^2, and the closed forms still hold 1e-10 there)."""
+    p = ff.Params(L=12.0, M=24, a=A, Sigma=0.9, M_G=10, R_c=4.0, eta=1.3, Sigma_D=1.1)
+    rng = np.random.default_rng(23)
+    Y = rng.uniform(0.0, 12.0, size=(5, 3))
+    Y[1] = Y[0]
+    F, T = rng.normal(size=(5, 3)), rng.normal(size=(5, 3))
+    dV, dW = ff.pair_correction(p, Y, F, T)
+    assert np.isfinite(dV).all() and np.isfinite(dW).all()
+    step = 1e-3 * p.sigma * np.array([0.48, -0.6, 0.64])
+    Yp, Ym = Y.copy(), Y.copy()
+    Yp[1] += step
+    Ym[1] -= step
+    (pV, pW), (mV, mW) = ff.pair_correction(p, Yp, F, T), ff.pair_correction(p, Ym, F, T)
+    assert np.abs(dV - 0.5 * (pV + mV)).max() < 1e-6 * np.abs(dV).max()
+    assert np.abs(dW - 0.5 * (pW + mW)).max() < 1e-6 * np.abs(dW).max()
+    # and the coincident pair contributes the self-correction values
+    solo = ff.pair_correction(p, np.delete(Y, 1, axis=0), np.delete(F, 1, axis=0), np.delete(T, 1, axis=0))
+    from oracle import closed_forms as cf
+    extra = cf.self_correction_VF(A, p.sigma, p.Sigma, p.eta) * F[1]
+    assert np.allclose(dV[0] - solo[0][0], extra, rtol=0, atol=1e-13)
