@@ -21,9 +21,10 @@
  *  - Particle arrays are DEVICE pointers to N x 3 row-major FP64 values
  *    (x, y, z interleaved per particle) on the device the plan was created on.
  *    The caller owns them.  Outputs are written in the caller's particle order.
- *  - Positions may lie anywhere; they are wrapped into [0, L).  Non-finite
- *    positions (and ones too large to wrap) are replaced by 0 and reported
- *    by fcm_plan_last_error().
+ *  - Positions may lie anywhere; they are wrapped into [0, L) by the exact
+ *    floating-point remainder (plus L for negative values; a result that
+ *    rounds to L becomes 0).  Non-finite positions are replaced by 0 and
+ *    reported by fcm_plan_last_error().
  *  - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
  *    and return without waiting; results are ready when the stream reaches
  *    them.  A plan owns scratch buffers, so concurrent calls on one plan race:

@@ -37,18 +37,22 @@ constexpr int kThreadSegment = 16;     // ordered by one thread, in registers
 constexpr int kWaveSegment = 64;       // ordered by one wavefront
 constexpr int kLdsSegment = 8192;      // ordered by a workgroup's bitonic sort in LDS
 
-// wrap into [0, L); non-finite values, and values too large for the wrap to
-// land in [0, L), become 0 and raise the plan's flag.  Every index derived
-// from the result is therefore in range.
+// wrap into [0, L): the floating-point remainder (exact for every finite y),
+// plus L when negative (one rounding, which may reach L: then 0).  Support
+// starts are integers decided from the wrapped value at grid points, so the
+// wrap must not round more than this: y - L floor(y / L) differs from it by
+// ulps when y lies periods away, or when y / L rounds up to an integer.
+// Non-finite values become 0 and raise the plan's flag; every index derived
+// from the result is in range.
 __device__ inline double wrap_coord(double y, double L, int* bad) {
     if (!isfinite(y)) {
         *bad = 1;
         return 0.0;
     }
-    double w = y - L * floor(y / L);
+    double w = fmod(y, L);
+    if (w < 0.0) w += L;
     if (w >= L) w -= L;
-    if (w < 0.0) w = 0.0;     // rounding just below 0
-    if (!(w < L)) {
+    if (!(w < L) || w < 0.0) {   // unreachable for finite y and L > 0
         *bad = 1;
         w = 0.0;
     }

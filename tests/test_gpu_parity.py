@@ -10,7 +10,9 @@ torques on and off, a separate torque width, standard FCM, a crowded box
 about 300 of them), a dense cluster (spreading tiles with ~1500 candidates),
 supports M_G = 15 and 16 on
 grids whose FP32 mobility runs in the tiled layout (the packed interpolation's
-widest form), and N = 1.
+widest form), N = 1, and a lattice of grid points given one to six periods
+away (the wrap must land exactly where the oracle's does, or a support start
+moves by one point).
 """
 
 import math
@@ -425,3 +427,73 @@ def test_mobility_repeat_equals_full_call(prec):
     from paper_2310_12651_amd import FCMError
     with pytest.raises(FCMError):
         plan.mobility_repeat(F2, T2)
+
+
+def _lattice_case(M, dx, N, seed):
+    """N distinct grid points j dx with odd indices, each coordinate shifted by
+    n L, n in [-6, 6]; in eight of them one coordinate is n L exactly (four)
+    or one ulp below it (four), which wraps to 0 or just below L: next to the
+    odd sites, so no two particles come closer than dx."""
+    rng = np.random.default_rng(seed)
+    L = M * dx
+    h = M // 2
+    sites = rng.choice(h ** 3, size=N, replace=False)
+    j = 2 * np.stack([sites % h, (sites // h) % h, sites // (h * h)], 1).astype(np.float64) + 1.0
+    n = rng.integers(-6, 7, size=(N, 3)).astype(np.float64)
+    Y = j * dx + n * L
+    for i in range(8):
+        a = i % 3
+        Y[i, a] = n[i, a] * L if i < 4 else n[i, a] * L - np.spacing(abs(n[i, a] * L) + L)
+    d = Y[:, None, :] - Y[None, :, :]
+    d -= L * np.round(d / L)
+    r = np.sqrt(np.sum(d * d, -1)) + np.eye(N) * L
+    assert r.min() > 0.99 * dx, r.min()
+    return Y, L, rng
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,dx,MG", [(54, 0.3, 10), (64, 0.35, 12)], ids=["rowmajor54", "tiled64"])
+def test_lattice_positions_periods_away_match_oracle(M, dx, MG, prec):
+    """Support starts are integers decided at grid points: the position wraps
+    by the exact remainder on both sides, so each support lies where the
+    oracle puts it (a window one point off changes V by the kernel's tail)."""
+    Y, L, rng = _lattice_case(M, dx, 80, zlib.crc32(b"lattice%d" % M))
+    F, T = rng.normal(size=(len(Y), 3)), rng.normal(size=(len(Y), 3))
+    p = ff.Params(L=L, M=M, a=A, Sigma=2.0 * dx, M_G=MG, R_c=2.9)
+    Vr, Wr = ff.mobility(p, Y, F, T)
+    w = dict(N=len(Y), L=L, a=A, Sigma=2.0 * dx, grid=M, M_G=MG, R_c=2.9)
+    plan = make_plan(w, 0 if prec == "fp64" else 1)
+    try:
+        V, W = plan.mobility(dev(Y), dev(F), dev(T))
+        V, W = host(V), host(W)
+        assert plan.last_error() == 0
+    finally:
+        plan.close()
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert normwise(V, Vr) < tol and normwise(W, Wr) < tol, (normwise(V, Vr), normwise(W, Wr))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_coincident_centres_match_oracle(prec):
+    """Distinct particles at exactly the same point (ten pairs and a triple
+    among 40): the pair corrections take App. B's r -> 0 limits on both sides
+    (the oracle's closed forms divide by r, so it switches to the limits at
+    r = 0; the kernel below 1e-3 sigma)."""
+    rng = np.random.default_rng(zlib.crc32(b"coincident"))
+    L, M = 14.0, 36
+    Y = rng.uniform(-L, 2.0 * L, size=(40, 3))
+    for i in range(10):
+        Y[2 * i + 1] = Y[2 * i]
+    Y[21] = Y[22] = Y[20]
+    F, T = rng.normal(size=(40, 3)), rng.normal(size=(40, 3))
+    w = dict(N=40, L=L, a=A, Sigma=0.75, grid=M, M_G=10, R_c=4.5)
+    Vr, Wr = ff.mobility(oracle_params(w), Y, F, T)
+    assert np.isfinite(Vr).all() and np.isfinite(Wr).all()
+    plan = make_plan(w, 0 if prec == "fp64" else 1)
+    try:
+        V, W = plan.mobility(dev(Y), dev(F), dev(T))
+        V, W = host(V), host(W)
+    finally:
+        plan.close()
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert normwise(V, Vr) < tol and normwise(W, Wr) < tol, (normwise(V, Vr), normwise(W, Wr))
