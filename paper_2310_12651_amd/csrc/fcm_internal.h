@@ -112,7 +112,7 @@ struct PairArgs {
     double Lx, Ly, Lz;             // box sides
     double iLx, iLy, iLz;          // and their reciprocals
     double cwx, cwy, cwz;          // cell widths
-    double rc2;
+    double rc2;                    // smallest r^2 with sqrt(r^2) >= R_c (the cut-off test)
     double eta, sigma, sigmaD, Sigma, SigmaD;
     double selfVF, selfOT;
     int with_pairs;                // 0 = only self corrections (R_c = 0)

@@ -176,13 +176,22 @@ __device__ inline void add_pair(double x0, double x1, double x2, double r2, cons
     w[2] += c.fof * (F0 * x1 - F1 * x0) + c.Aot * T2 + c.Bot * h2 * hT;
 }
 
+// r^2 with every product and sum rounded, (x0^2 + x1^2) + x2^2: the cut-off
+// test r^2 < rc2 then decides as sqrt(r^2) < R_c does on that sum (rc2 is the
+// smallest double whose square root reaches R_c), pairs within ulps of R_c
+// included
+__device__ inline double dist2_rounded(double x0, double x1, double x2) {
+#pragma clang fp contract(off)
+    return (x0 * x0 + x1 * x1) + x2 * x2;
+}
+
 // minimum image of p - o in the box of sides a.Lx, a.Ly, a.Lz
 __device__ inline double4 min_image(double4 p, double4 o, const PairArgs& a) {
     double x0 = p.x - o.x, x1 = p.y - o.y, x2 = p.z - o.z;
     x0 -= a.Lx * rint(x0 * a.iLx);
     x1 -= a.Ly * rint(x1 * a.iLy);
     x2 -= a.Lz * rint(x2 * a.iLz);
-    return make_double4(x0, x1, x2, x0 * x0 + x1 * x1 + x2 * x2);
+    return make_double4(x0, x1, x2, dist2_rounded(x0, x1, x2));
 }
 
 // The candidates of particle j's z layer `layer` (0, 1, 2 = cz-1, cz, cz+1)
@@ -459,7 +468,12 @@ hipError_t launch_pair(const fcm_plan_impl* P, double* V, double* W, bool /*torq
     a.cwx = P->L / P->m;
     a.cwy = P->Ly / P->mcy;
     a.cwz = P->Lz / P->mcz;
-    a.rc2 = P->rc * P->rc;
+    // the smallest double whose (correctly rounded) square root reaches R_c:
+    // r2 < rc2 exactly when sqrt(r2) < R_c, as sqrt is monotone
+    double t = P->rc * P->rc;
+    while (t > 0.0 && sqrt(nextafter(t, 0.0)) >= P->rc) t = nextafter(t, 0.0);
+    while (sqrt(t) < P->rc) t = nextafter(t, INFINITY);
+    a.rc2 = t;
     a.eta = P->eta;
     a.sigma = P->sigma;
     a.sigmaD = P->sigmaD;

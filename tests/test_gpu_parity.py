@@ -497,3 +497,35 @@ def test_coincident_centres_match_oracle(prec):
         plan.close()
     tol = 1e-10 if prec == "fp64" else 1e-5
     assert normwise(V, Vr) < tol and normwise(W, Wr) < tol, (normwise(V, Vr), normwise(W, Wr))
+
+
+def _cutoff_case(L, Rc, npairs, seed):
+    """Pairs whose separation is R_c to within two ulps, spread over the box."""
+    rng = np.random.default_rng(seed)
+    P = rng.uniform(0.0, L, size=(npairs, 3))
+    d = rng.normal(size=(npairs, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    Q = P + Rc * d * (1.0 + rng.integers(-2, 3, size=(npairs, 1)) * 2.0 ** -52)
+    return np.concatenate([P, Q]), rng
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pairs_at_the_cutoff_match_oracle(prec):
+    """The cut-off r < R_c decides a pair within ulps of R_c as the oracle
+    does: r^2 summed (x0^2 + x1^2) + x2^2 with each step rounded, against the
+    smallest double whose square root reaches R_c (a fused r^2, or r^2 <
+    R_c * R_c, flips about one such pair in twenty; a flipped pair moves V by
+    the correction at R_c, ~1e-4 here)."""
+    L, Rc = 24.0, 2.5
+    Y, rng = _cutoff_case(L, Rc, 60, zlib.crc32(b"cutoff"))
+    F, T = rng.normal(size=(len(Y), 3)), rng.normal(size=(len(Y), 3))
+    w = dict(N=len(Y), L=L, a=A, Sigma=0.75, grid=48, M_G=10, R_c=Rc)
+    Vr, Wr = ff.mobility(oracle_params(w), Y, F, T)
+    plan = make_plan(w, 0 if prec == "fp64" else 1)
+    try:
+        V, W = plan.mobility(dev(Y), dev(F), dev(T))
+        V, W = host(V), host(W)
+    finally:
+        plan.close()
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert normwise(V, Vr) < tol and normwise(W, Wr) < tol, (normwise(V, Vr), normwise(W, Wr))
