@@ -10,9 +10,10 @@ torques on and off, a separate torque width, standard FCM, a crowded box
 about 300 of them), a dense cluster (spreading tiles with ~1500 candidates),
 supports M_G = 15 and 16 on
 grids whose FP32 mobility runs in the tiled layout (the packed interpolation's
-widest form), N = 1, and a lattice of grid points given one to six periods
+widest form), N = 1, a lattice of grid points given one to six periods
 away (the wrap must land exactly where the oracle's does, or a support start
-moves by one point).
+moves by one point), positions up to 1e9 box lengths away, coincident
+centres, and pairs within two ulps of the cut-off.
 """
 
 import math
@@ -525,6 +526,33 @@ def test_pairs_at_the_cutoff_match_oracle(prec):
     try:
         V, W = plan.mobility(dev(Y), dev(F), dev(T))
         V, W = host(V), host(W)
+    finally:
+        plan.close()
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert normwise(V, Vr) < tol and normwise(W, Wr) < tol, (normwise(V, Vr), normwise(W, Wr))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_far_positions_match_oracle(prec):
+    """Finite positions up to 1e9 box lengths away wrap by the exact remainder
+    on both sides (no position is too far to wrap), and such a call raises no
+    flag; infinities still do."""
+    rng = np.random.default_rng(zlib.crc32(b"far"))
+    L, N = 20.0, 40
+    Y = rng.uniform(0.0, L, size=(N, 3)) + L * np.round(10.0 ** rng.uniform(0.0, 9.0, size=(N, 3)) *
+                                                         rng.choice([-1.0, 1.0], size=(N, 3)))
+    F, T = rng.normal(size=(N, 3)), rng.normal(size=(N, 3))
+    w = dict(N=N, L=L, a=A, Sigma=0.8, grid=48, M_G=10, R_c=4.0)
+    Vr, Wr = ff.mobility(oracle_params(w), Y, F, T)
+    plan = make_plan(w, 0 if prec == "fp64" else 1)
+    try:
+        V, W = plan.mobility(dev(Y), dev(F), dev(T))
+        V, W = host(V), host(W)
+        assert plan.last_error() == 0
+        Yi = Y.copy()
+        Yi[5, 2] = np.inf
+        plan.mobility(dev(Yi), dev(F), dev(T))
+        assert plan.last_error() == -5
     finally:
         plan.close()
     tol = 1e-10 if prec == "fp64" else 1e-5
